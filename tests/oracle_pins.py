@@ -1,0 +1,444 @@
+"""Pins of the CPU oracle: checks against things other than the oracle itself.
+
+Each ``pin_*`` function takes the oracle module and a loaded library handle
+and raises AssertionError when the oracle disagrees with the pin.  The
+regular tests run them on the real oracle; the mutation tests run them on
+copies of the oracle with a planted mistake and require that some pin fails.
+
+Which pin covers which oracle function:
+  healpix_ring  pin_healpix_golden_nside1, pin_healpix_structure
+  check_tiling  pin_tiling
+  walk_one      pin_walk_golden, pin_uniform_closed_form, pin_chord_invariants,
+                pin_bruteforce, pin_amanatides_woo, pin_negation, pin_edge_cases,
+                pin_deep_tree, pin_kahan_compensation
+  columns       pin_linearity_and_refinement, pin_columns_consistency, pin_kahan_bound
+  gradient      pin_gradient
+"""
+
+import os
+
+import numpy as np
+
+import workloads as W
+from reference_geometry import (amanatides_woo, bruteforce_chords, exit_time, fnv_sequence_hash,
+                                leaf_boxes, random_unit_vectors)
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def _frac(s):
+    if "/" in s:
+        a, b = s.split("/")
+        return float(a) / float(b)
+    return float(s)
+
+
+# ---------------------------------------------------------------- HEALPix
+
+def pin_healpix_golden_nside1(orc, lib):
+    rows = [ln.split() for ln in open(os.path.join(GOLDEN, "healpix_nside1.txt"))
+            if ln.strip() and not ln.startswith("#")]
+    d = orc.healpix_ring(1, lib=lib)
+    assert d.shape == (12, 3)
+    for pix, zs, ps in rows:
+        z = _frac(zs)
+        phi = np.pi * _frac(ps)
+        st = np.sqrt(1.0 - z * z)
+        want = np.array([st * np.cos(phi), st * np.sin(phi), z])
+        assert np.abs(d[int(pix)] - want).max() <= 1e-15, (pix, d[int(pix)], want)
+
+
+def pin_healpix_structure(orc, lib):
+    for nside in (1, 2, 3, 4, 8):
+        d = orc.healpix_ring(nside, lib=lib)
+        npix = 12 * nside * nside
+        assert d.shape == (npix, 3)
+        assert np.abs(np.linalg.norm(d, axis=1) - 1.0).max() <= 1e-15
+        assert np.abs(d.sum(axis=0)).max() <= 1e-13
+        # closed under negation
+        for v in d:
+            assert np.abs(d + v).sum(axis=1).min() <= 1e-14
+        # rings: consecutive pixels with equal z; sizes 4i (caps) / 4 nside (belt)
+        z = d[:, 2]
+        breaks = np.nonzero(np.diff(z) != 0)[0] + 1
+        rings = np.split(np.arange(npix), breaks)
+        assert len(rings) == 4 * nside - 1
+        before = 0
+        for i, r in enumerate(rings, start=1):
+            want = 4 * min(i, nside, 4 * nside - i)
+            assert len(r) == want, (nside, i, len(r), want)
+            zi = z[r[0]]
+            # equal-area zone identity: area fraction north of the ring centre
+            frac = (before + 0.5 * len(r)) / npix
+            assert abs((1.0 - zi) / 2.0 - frac) <= 1e-15, (nside, i)
+            # azimuths ascend with constant spacing 2 pi / (ring size)
+            phi = np.mod(np.arctan2(d[r, 1], d[r, 0]), 2 * np.pi)
+            if len(r) > 1:
+                assert np.abs(np.diff(phi) - 2 * np.pi / len(r)).max() <= 1e-12
+            before += len(r)
+        # z strictly decreasing from ring to ring (north to south)
+        assert np.all(np.diff(z[[r[0] for r in rings]]) < 0)
+
+
+# ---------------------------------------------------------------- tiling
+
+def pin_tiling(orc, lib):
+    t = W.random_octree(4, 0.4, 11, min_level=1)
+    assert orc.check_tiling(t.keys, t.levels, 4, lib=lib) == orc.OK
+    u = W.uniform_octree(2, np.ones(64))
+    assert orc.check_tiling(u.keys, u.levels, 2, lib=lib) == orc.OK
+    k, L = t.keys.copy(), t.levels.copy()
+    k[[3, 4]] = k[[4, 3]]
+    L[[3, 4]] = L[[4, 3]]
+    assert orc.check_tiling(k, L, 4, lib=lib) == orc.ERR_UNSORTED
+    # gap: drop a leaf
+    assert orc.check_tiling(np.delete(t.keys, 5), np.delete(t.levels, 5), 4, lib=lib) == orc.ERR_TILING
+    # overlap: make a leaf coarser than its span
+    i = int(np.nonzero(t.levels == 4)[0][1])
+    L = t.levels.copy()
+    L[i] = 3
+    assert orc.check_tiling(t.keys, L, 4, lib=lib) == orc.ERR_TILING
+    # misaligned key (level-3 leaf moved by one fine cell)
+    j = int(np.nonzero(t.levels <= 3)[0][2])
+    k = t.keys.copy()
+    k[j] += np.uint64(1)
+    assert orc.check_tiling(k, t.levels, 4, lib=lib) != orc.OK
+    # wrong end: last leaf missing
+    assert orc.check_tiling(t.keys[:-1], t.levels[:-1], 4, lib=lib) == orc.ERR_TILING
+    # level beyond depth
+    L = u.levels.copy()
+    L[0] = 3
+    assert orc.check_tiling(u.keys, L, 2, lib=lib) != orc.OK
+
+
+# ---------------------------------------------------------------- walks
+
+def golden_trees():
+    t1 = W.Octree(1, np.arange(8, dtype=np.uint64), np.full(8, 1, dtype=np.uint8),
+                  np.arange(1, 9, dtype=np.float64))
+    keys = np.concatenate([np.arange(8), 8 * np.arange(1, 8)]).astype(np.uint64)
+    levels = np.array([2] * 8 + [1] * 7, dtype=np.uint8)
+    rho = np.concatenate([1.0 + np.arange(8) / 10.0, 10.0 * np.arange(1, 8)])
+    t2 = W.Octree(2, keys, levels, rho)
+    return {"T1": t1, "T2": t2}
+
+
+def pin_walk_golden(orc, lib):
+    trees = golden_trees()
+    r3 = np.sqrt(3.0)
+
+    def val(s):
+        if s == "d":
+            return 1.0 / r3
+        if s.endswith("r3"):
+            return float(s[:-2]) * r3
+        return float(s)
+
+    for ln in open(os.path.join(GOLDEN, "walk_examples.txt")):
+        if not ln.strip() or ln.startswith("#"):
+            continue
+        f = ln.split()
+        tree = trees[f[1]]
+        Q = [val(x) for x in f[2:5]]
+        m = [val(x) for x in f[5:8]]
+        N, tx = val(f[8]), val(f[9])
+        vis = [int(x) for x in f[10].split(",")]
+        r = orc.walk_one(tree, Q, m, lib=lib)
+        assert r["status"] == orc.OK, f[0]
+        assert list(r["visited"]) == vis, (f[0], list(r["visited"]), vis)
+        assert abs(r["N"] - N) <= 1e-15 * N, (f[0], r["N"], N)
+        assert abs(r["texit"] - tx) <= 1e-15 * tx, (f[0], r["texit"], tx)
+
+
+def _test_rays(seed, count):
+    rng = np.random.default_rng(seed)
+    Q = rng.random((count, 3))
+    m = random_unit_vectors(count, seed + 1)
+    return Q, m
+
+
+def _special_dirs(orc, lib):
+    axis = np.array([[1, 0, 0], [-1, 0, 0], [0, 1, 0], [0, -1, 0], [0, 0, 1], [0, 0, -1]], float)
+    diag = np.array([[1, 1, 1], [-1, 1, -1], [1, -1, 0], [0, 1, 1]], float)
+    diag /= np.linalg.norm(diag, axis=1)[:, None]
+    return np.vstack([axis, diag, orc.healpix_ring(2, lib=lib)])
+
+
+def pin_uniform_closed_form(orc, lib):
+    t = W.random_octree(5, 0.45, 21, min_level=1)
+    rho0 = 2.5
+    t.rho = np.full(t.n, rho0)
+    Q, m = _test_rays(22, 150)
+    dirs = _special_dirs(orc, lib)
+    cases = list(zip(Q, m)) + [(Q[i % len(Q)], d) for i, d in enumerate(dirs)]
+    # cell-centre and face-aligned sources with HEALPix directions
+    for q in ([0.5, 0.5, 0.5], [0.25, 0.0, 0.75], [1 / 64, 3 / 64, 5 / 64]):
+        cases += [(np.array(q), d) for d in dirs]
+    for q, d in cases:
+        r = orc.walk_one(t, q, d, lib=lib)
+        te = exit_time(q, d)
+        assert r["status"] == orc.OK
+        assert abs(r["N"] - rho0 * te) <= 1e-13 * rho0 * te, (q, d, r["N"], rho0 * te)
+        assert abs(r["texit"] - te) <= 1e-13 * te
+
+
+def pin_chord_invariants(orc, lib):
+    t = W.random_octree(5, 0.45, 31, min_level=1)
+    sizes = t.sizes() / float(1 << t.depth)
+    Q, m = _test_rays(32, 150)
+    dirs = _special_dirs(orc, lib)
+    cases = list(zip(Q, m)) + [(np.array([0.5, 0.5, 0.5]), d) for d in dirs]
+    for q, d in cases:
+        r = orc.walk_one(t, q, d, lib=lib)
+        te = exit_time(q, d)
+        c = r["chords"]
+        assert r["status"] == orc.OK and r["steps"] == len(c)
+        assert np.all(c >= 0.0)
+        assert abs(c.sum() - te) <= 1e-13 * te
+        assert np.all(c <= np.sqrt(3.0) * sizes[r["visited"]] * (1 + 1e-12))
+    # generic rays never need the clamp; it only absorbs rounding at exact
+    # lattice crossings (the source at the box centre above)
+    for q, d in zip(Q, m):
+        assert orc.walk_one(t, q, d, lib=lib)["clamps"] == 0
+
+
+def pin_bruteforce(orc, lib):
+    for seed, D, p in ((41, 4, 0.5), (42, 3, 0.7), (43, 4, 0.3)):
+        t = W.random_octree(D, p, seed, min_level=1)
+        boxes = leaf_boxes(t)
+        Q, m = _test_rays(seed + 100, 120)
+        dirs = _special_dirs(orc, lib)
+        h = 1.0 / (1 << D)
+        face = np.array([3 * h, 0.5, 5 * h])
+        cases = list(zip(Q, m)) + [(face, d) for d in dirs] + [(np.array([0.5 * h] * 3), d) for d in dirs]
+        for q, d in cases:
+            r = orc.walk_one(t, q, d, lib=lib)
+            chord, entry, te = bruteforce_chords(t, q, d, boxes)
+            assert r["status"] == orc.OK
+            nb = float(np.dot(t.rho, chord))
+            assert abs(r["N"] - nb) <= 1e-12 * nb, (seed, q, d, r["N"], nb)
+            # per-leaf chords agree; every leaf with a positive chord is visited
+            walk_chord = np.zeros(t.n)
+            np.add.at(walk_chord, r["visited"], r["chords"])
+            assert np.abs(walk_chord - chord).max() <= 1e-12
+            assert set(np.nonzero(chord > 1e-12)[0]) <= set(r["visited"].tolist())
+            # order of the positive-chord leaves follows the entry times
+            pos = [i for i, c in zip(r["visited"], r["chords"]) if c > 1e-12]
+            assert pos == sorted(pos, key=lambda i: entry[i])
+
+
+def pin_amanatides_woo(orc, lib):
+    for D in (3, 4):
+        n = 1 << D
+        t = W.uniform_octree(D, np.exp(np.random.default_rng(D).standard_normal(8 ** D)))
+        Q, m = _test_rays(50 + D, 150)
+        for q, d in zip(Q, m):
+            r = orc.walk_one(t, q, d, lib=lib)
+            cells = amanatides_woo(n, q, d)
+            want = [int(W.morton_encode(c[0], c[1], c[2], D)) for c in cells]
+            assert list(r["visited"]) == want, (D, q, d)
+
+
+def pin_negation(orc, lib):
+    t = W.random_octree(4, 0.5, 61, min_level=1)
+    rho0 = 0.75
+    t.rho = np.full(t.n, rho0)
+    Q, m = _test_rays(62, 100)
+    for q, d in zip(Q, m):
+        a = orc.walk_one(t, q, d, lib=lib)["N"]
+        b = orc.walk_one(t, q, -d, lib=lib)["N"]
+        full = rho0 * (exit_time(q, d) + exit_time(q, -d))
+        assert abs(a + b - full) <= 1e-13 * full
+
+
+def pin_linearity_and_refinement(orc, lib):
+    t = W.random_octree(4, 0.5, 71, min_level=1)
+    rng = np.random.default_rng(72)
+    r1, r2 = np.exp(rng.standard_normal(t.n)), np.exp(rng.standard_normal(t.n))
+    Q, m = _test_rays(73, 40)
+    dirs = orc.healpix_ring(1, lib=lib)
+    a, b = 0.3, 1.7
+    n1 = orc.columns(t, Q, dirs, rho=r1, lib=lib)["N"]
+    n2 = orc.columns(t, Q, dirs, rho=r2, lib=lib)["N"]
+    n12 = orc.columns(t, Q, dirs, rho=a * r1 + b * r2, lib=lib)["N"]
+    assert np.abs(n12 - (a * n1 + b * n2)).max() <= 1e-12 * np.abs(n12).max()
+    t.rho = r1
+    coarse = [int(i) for i in np.nonzero(t.levels < t.depth)[0][:5]]
+    for i in coarse:
+        s = W.split_leaf(t, i)
+        assert orc.check_tiling(s.keys, s.levels, s.depth, lib=lib) == orc.OK
+        ns = orc.columns(s, Q, dirs, lib=lib)["N"]
+        assert np.abs(ns - n1).max() <= 1e-12 * np.abs(n1).max()
+    # random directions too
+    for q, d in zip(Q, m):
+        base = orc.walk_one(t, q, d, lib=lib)["N"]
+        s = W.split_leaf(t, coarse[0])
+        assert abs(orc.walk_one(s, q, d, lib=lib)["N"] - base) <= 1e-12 * base
+
+
+def pin_columns_consistency(orc, lib):
+    """columns() equals walk_one() ray by ray; the hash is FNV over the
+    visited sequence; A = exp(-kappa N)."""
+    t = W.random_octree(4, 0.5, 81, min_level=1)
+    Q, _ = _test_rays(82, 10)
+    dirs = orc.healpix_ring(2, lib=lib)
+    kappa = 0.7
+    out = orc.columns(t, Q, dirs, kappa, rho32=t.rho.astype(np.float32), lib=lib)
+    assert out["status"] == orc.OK and out["clamps"] == 0
+    for s in range(len(Q)):
+        for d in range(len(dirs)):
+            r = orc.walk_one(t, Q[s], dirs[d], rho32=t.rho.astype(np.float32), lib=lib)
+            assert out["N"][s, d] == r["N"] and out["steps"][s, d] == r["steps"]
+            assert out["N32"][s, d] == r["N32"]
+            assert int(out["hash"][s, d]) == r["hash"] == fnv_sequence_hash(r["visited"])
+            assert abs(out["A"][s, d] - np.exp(-kappa * r["N"])) <= 1e-15
+            assert abs(out["A32"][s, d] - np.exp(-kappa * r["N32"])) <= 3e-7 * out["A32"][s, d]
+
+
+def pin_edge_cases(orc, lib):
+    # minimal tree, D = 1
+    t = W.uniform_octree(1, np.arange(1.0, 9.0))
+    r = orc.walk_one(t, [0.5, 0.5, 0.5], [1, 0, 0], lib=lib)
+    assert r["status"] == orc.OK and list(r["visited"]) == [7] and r["N"] == 8 * 0.5
+    # source on the lower face, walking down: leaves at once
+    r = orc.walk_one(t, [0.0, 0.25, 0.25], [-1, 0, 0], lib=lib)
+    assert r["status"] == orc.OK and r["steps"] == 1 and r["N"] == 0.0
+    # last representable coordinate below 1
+    top = np.nextafter(1.0, 0.0)
+    r = orc.walk_one(t, [top, top, top], [1, 0, 0], lib=lib)
+    assert r["status"] == orc.OK and list(r["visited"]) == [7]
+    assert abs(r["N"] - 8 * (1.0 - top)) <= 1e-30
+    # a denormal direction component does not bound the walk
+    r = orc.walk_one(t, [0.25, 0.25, 0.25], [1e-310, 0, 1], lib=lib)
+    assert r["status"] == orc.OK and list(r["visited"]) == [0, 4]
+    # a ray running inside the face plane z = 1/2 belongs to the upper cells
+    r = orc.walk_one(t, [0.25, 0.25, 0.5], [1, 0, 0], lib=lib)
+    assert list(r["visited"]) == [4, 5]
+    # errors: source outside [0,1)^3, zero or non-finite direction
+    assert orc.walk_one(t, [1.0, 0.5, 0.5], [1, 0, 0], lib=lib)["status"] == orc.ERR_RANGE
+    assert orc.walk_one(t, [-1e-300, 0.5, 0.5], [1, 0, 0], lib=lib)["status"] == orc.ERR_RANGE
+    assert orc.walk_one(t, [np.nan, 0.5, 0.5], [1, 0, 0], lib=lib)["status"] == orc.ERR_RANGE
+    assert orc.walk_one(t, [0.5, 0.5, 0.5], [0, 0, 0], lib=lib)["status"] == orc.ERR_ARG
+    assert orc.walk_one(t, [0.5, 0.5, 0.5], [np.inf, 0, 0], lib=lib)["status"] == orc.ERR_ARG
+
+
+def deep_tree(depth=21):
+    """The cell at the origin corner is split at every level; all others are
+    leaves.  7 leaves per level plus 8 at the maximum depth."""
+    keys, levels = [], []
+    for L in range(depth):
+        span = 8 ** (depth - L - 1)
+        for c in range(1, 8):
+            keys.append(c * span)
+            levels.append(L + 1)
+    keys.append(0)
+    levels.append(depth)
+    # the origin cell at the maximum depth has 7 siblings already listed at level `depth`
+    order = np.argsort(np.array(keys, dtype=np.uint64), kind="stable")
+    k = np.array(keys, dtype=np.uint64)[order]
+    lv = np.array(levels, dtype=np.uint8)[order]
+    rho = np.exp(np.random.default_rng(depth).standard_normal(len(k)))
+    return W.Octree(depth, k, lv, rho)
+
+
+def pin_deep_tree(orc, lib):
+    t = deep_tree(21)
+    assert orc.check_tiling(t.keys, t.levels, 21, lib=lib) == orc.OK
+    boxes = leaf_boxes(t)
+    h = 2.0 ** -21
+    cases = [([0.3 * h, 0.7 * h, 0.2 * h], d) for d in random_unit_vectors(30, 91)]
+    cases += [([0.9, 0.9, 0.9], -np.ones(3) / np.sqrt(3.0)), ([h, 2 * h, 3 * h], [1, 0, 0])]
+    for q, d in cases:
+        r = orc.walk_one(t, q, d, lib=lib)
+        chord, _, te = bruteforce_chords(t, np.array(q), np.array(d, float), boxes)
+        nb = float(np.dot(t.rho, chord))
+        assert r["status"] == orc.OK
+        assert abs(r["N"] - nb) <= 1e-12 * nb
+        assert abs(r["texit"] - te) <= 1e-13 * te
+
+
+def pin_kahan_compensation(orc, lib):
+    """A ray whose first product is 2**17 ulps larger than each later one by a
+    factor that rounds them away in plain FP32 summation; the compensated sum
+    keeps them (error within 2 ulps of the exact sum of the FP32 products)."""
+    D = 7
+    n = 1 << D
+    grid = np.zeros((n, n, n))
+    grid[:, 0, 0] = 10.0
+    t = W.threshold_refined_octree(grid, 0, 1.0)
+    row = np.nonzero((t.levels == D) & np.all(t.anchors()[:, 1:] == 0, axis=1))[0]
+    assert len(row) == n
+    rho = np.ones(t.n)
+    rho[row] = 7.8e-4
+    rho[row[0]] = 32768.0
+    t.rho = rho
+    r32 = rho.astype(np.float32)
+    q = np.array([0.5 / n, 0.5 / n, 0.5 / n])
+    r = orc.walk_one(t, q, [1, 0, 0], rho32=r32, lib=lib)
+    terms = [np.float32(r32[i]) * np.float32(c) for i, c in zip(r["visited"], r["chords"])]
+    exact = float(np.sum(np.array(terms, dtype=np.float64)))
+    naive = np.float32(0)
+    for x in terms:
+        naive = np.float32(naive + x)
+    assert abs(float(naive) - exact) > 20 * 2.0 ** -24 * exact  # the case discriminates
+    assert abs(r["N32"] - exact) <= 2 * 2.0 ** -24 * exact
+
+
+def pin_kahan_bound(orc, lib):
+    """FP32 compensated columns stay within 1e-5 (relative) of FP64 on a
+    lognormal AMR cloud."""
+    g = W.gaussian_random_field(32, -4.0, 5)
+    rho = W.lognormal(g, 2.0)
+    t = W.threshold_refined_octree(rho, 3, 2.0 * rho.mean())
+    src = W.random_points(30, 6)
+    out = orc.columns(t, src, orc.healpix_ring(2, lib=lib), 1.0, rho32=t.rho.astype(np.float32),
+                      lib=lib)
+    rel = np.abs(out["N32"].astype(np.float64) - out["N"]) / out["N"]
+    assert rel.max() <= 1e-5
+
+
+def pin_gradient(orc, lib):
+    t = W.random_octree(3, 0.5, 101, min_level=1)
+    src = W.random_points(12, 102)
+    dirs = orc.healpix_ring(1, lib=lib)
+    g = np.random.default_rng(103).standard_normal((len(src), len(dirs)))
+    grad = orc.gradient(t, src, dirs, g, lib=lib)
+    boxes = leaf_boxes(t)
+    want = np.zeros(t.n)
+    for s in range(len(src)):
+        for d in range(len(dirs)):
+            want += g[s, d] * bruteforce_chords(t, src[s], dirs[d], boxes)[0]
+    scale = np.abs(want).max()
+    assert np.abs(grad - want).max() <= 1e-12 * scale
+    N = orc.columns(t, src, dirs, lib=lib)["N"]
+    assert abs(np.dot(t.rho, grad) - np.sum(g * N)) <= 1e-12 * np.sum(np.abs(g * N))
+    # central differences (N is linear in rho: exact up to rounding)
+    for k in (0, t.n // 2, t.n - 1):
+        h = 1e-3 * t.rho[k]
+        rp, rm = t.rho.copy(), t.rho.copy()
+        rp[k] += h
+        rm[k] -= h
+        dp = orc.columns(t, src, dirs, rho=rp, lib=lib)["N"]
+        dm = orc.columns(t, src, dirs, rho=rm, lib=lib)["N"]
+        fd = float(np.sum(g * (dp - dm) / (2 * h)))
+        assert abs(fd - grad[k]) <= 1e-8 * scale
+
+
+ALL_PINS = [
+    pin_healpix_golden_nside1,
+    pin_healpix_structure,
+    pin_tiling,
+    pin_walk_golden,
+    pin_uniform_closed_form,
+    pin_chord_invariants,
+    pin_bruteforce,
+    pin_amanatides_woo,
+    pin_negation,
+    pin_linearity_and_refinement,
+    pin_columns_consistency,
+    pin_edge_cases,
+    pin_deep_tree,
+    pin_kahan_compensation,
+    pin_kahan_bound,
+    pin_gradient,
+]

@@ -1,0 +1,76 @@
+"""Planted mistakes: every pin battery must catch each of them.
+
+Each mutant is a copy of the oracle's C source with one plausible mistake
+(a dropped term, a wrong sign, a transposed bit, an off-by-one).  It is
+compiled to a temporary library and the full pin battery runs against it in
+a child process (so that a crash counts as caught).  A mutant that passes
+every pin would mean the pins cannot tell the mistake from the method.
+"""
+
+import os
+import subprocess
+import sys
+
+import pytest
+
+import oracle
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+
+MUTANTS = {
+    "anchor_not_aligned": ("anchor[a] = p[a] - p[a] % size;", "anchor[a] = p[a];"),
+    "far_plane_sign": ("int64_t plane = m[a] > 0.0 ? anchor[a] + size : anchor[a];",
+                       "int64_t plane = anchor[a] + size;"),
+    "morton_y_z_swapped": ("k |= (uint64_t)((y >> b) & 1) << (3 * b + 1);",
+                           "k |= (uint64_t)((y >> b) & 1) << (3 * b + 2);"),
+    "lookup_off_by_one": ("if (keys[mid] <= k) lo = mid; else hi = mid;",
+                          "if (keys[mid] < k) lo = mid; else hi = mid;"),
+    "t_in_not_advanced": ("            t_in = t_out;\n        }", "        }"),
+    "dropped_accumulation": ("N = N + rho[i] * l;", "N = rho[i] * l;"),
+    "negative_step_stays": ("p[a] = m[a] > 0.0 ? anchor[a] + size : anchor[a] - 1;",
+                            "p[a] = m[a] > 0.0 ? anchor[a] + size : anchor[a];"),
+    "single_axis_at_ties": ("if (bounding[a] && tf[a] == t_out) {",
+                            "if (bounding[a] && tf[a] == t_out && !out) { out = 2;"),
+    "kahan_no_compensation": ("c = (t - S) - y;", "c = 0.0f;"),
+    "gradient_without_chord": ("grad[vis[j]] += gr * chords[j];", "grad[vis[j]] += gr;"),
+    "belt_shift_parity": ("((i - nside) % 2 == 0) ? 0.5 * dphi : 0.0;",
+                          "((i - nside) % 2 == 1) ? 0.5 * dphi : 0.0;"),
+    "cap_z_linear": ("z = 1.0 - (double)(i * i) / (3.0 * ns * ns);",
+                     "z = 1.0 - (double)(i) / (3.0 * ns * ns);"),
+    "exit_misses_low_face": ("if (p[a] < 0 || p[a] >= side) out = 1;",
+                             "if (p[a] >= side) out = 1;"),
+    "first_probe_rounded": ("for (int a = 0; a < 3; ++a) p[a] = (int64_t)floor(Q[a] * scale);",
+                            "for (int a = 0; a < 3; ++a) p[a] = (int64_t)floor(Q[a] * scale + 0.5);"),
+    "non_exit_axis_frozen": ("double x = fma(m[a], t_out, Q[a]) * scale;",
+                             "double x = (double)p[a];"),
+    "tiling_gap_ignored": ("if (keys[i] != expect) return ORC_ERR_TILING;", ""),
+}
+
+BATTERY = """
+import sys
+sys.path.insert(0, {root!r}); sys.path.insert(0, {here!r})
+import oracle, oracle_pins
+lib = oracle.load({lib!r})
+failed = []
+for pin in oracle_pins.ALL_PINS:
+    try:
+        pin(oracle, lib)
+    except Exception as e:
+        failed.append(pin.__name__)
+print("FAILED", len(failed), " ".join(failed))
+"""
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_pins_catch_mutant(name, tmp_path):
+    old, new = MUTANTS[name]
+    src = open(oracle._SRC).read()
+    assert src.count(old) == 1, f"mutation site not found: {name}"
+    path = tmp_path / "mutant.c"
+    path.write_text(src.replace(old, new))
+    lib = oracle.build(source=str(path), output=str(tmp_path / "libmutant.so"))
+    code = BATTERY.format(root=ROOT, here=HERE, lib=lib)
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
+    caught = r.returncode != 0 or ("FAILED 0" not in r.stdout)
+    assert caught, f"mutant {name} passed every pin: {r.stdout}"

@@ -1,0 +1,177 @@
+/*
+ * raytheia.h -- C ABI of the MI355X reverse ray-walk library.
+ *
+ * The library computes direction-dependent column integrals by reverse ray
+ * tracing (Zhu et al., "RAYTHEIA", sec. 2): for every source point p and
+ * every direction q, a ray starts at p and walks outward through a leaf-only
+ * linear octree (the AMR contribution grid, sec. 2.2), leaf by leaf (DDA
+ * stepping with a Morton-key lookup, sec. 2.3.1), takes the exact chord of
+ * each leaf by the slab method (sec. 2.3.2), and accumulates
+ *     N(p, q) = sum_k rho_k r_k        (the discrete integral of sec. 2.3)
+ * and the attenuation A = exp(-kappa N) (solution of the absorption-only
+ * transfer equation, sec. 2.1) up to the boundary of the unit box.
+ *
+ * Conventions (all calls):
+ *   - The domain is the unit box [0,1)^3; cells are half-open.  A tree of
+ *     maximum depth D (1..21) has finest cells of edge h = 2^-D.  A leaf's key
+ *     is the Morton code at depth D of its minimum corner (bit b of the
+ *     integer x coordinate -> key bit 3b, y -> 3b+1, z -> 3b+2); a leaf of
+ *     level L spans 8^(D-L) consecutive keys.
+ *   - "host" pointers are read during the call only.  "device" pointers are
+ *     HIP device memory owned by the caller; the library only borrows them.
+ *     The library never allocates device memory: the octree lives in a
+ *     caller-provided workspace.
+ *   - Every call returns an rt_status (0 = RT_OK, < 0 = error); nothing
+ *     throws or aborts.  On error, rt_last_error() gives a message (thread-
+ *     local).  Argument checks run synchronously on the host before any
+ *     device work is queued; device work is queued on the given stream
+ *     (a hipStream_t passed as void*, NULL = the default stream) and runs
+ *     asynchronously.
+ *   - Calls that launch kernels may run concurrently on different streams,
+ *     also on the same octree: the octree is read-only after building.
+ */
+#ifndef RAYTHEIA_H
+#define RAYTHEIA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    RT_OK = 0,
+    RT_ERR_ARG = -1,       /* null pointer, bad size, bad nside/depth, overflow */
+    RT_ERR_UNSORTED = -2,  /* leaf keys not strictly increasing */
+    RT_ERR_TILING = -3,    /* leaves misaligned, overlapping, gapped, level > D */
+    RT_ERR_RANGE = -4,     /* value outside its domain */
+    RT_ERR_DEVICE = -5,    /* a HIP runtime call failed */
+    RT_ERR_WORKSPACE = -6  /* workspace too small or misaligned */
+} rt_status;
+
+typedef enum {
+    RT_FP64 = 0,       /* rho f64, N/A f64: FP64 slab tests and FP64 accumulation */
+    RT_FP32_KAHAN = 1  /* rho f32, N/A f32: FP64 slab tests (same traversal as
+                          RT_FP64), rho*l summed in FP32 with Kahan compensation */
+} rt_precision;
+
+typedef struct rt_octree rt_octree; /* opaque host handle */
+
+/* ABI version of this header (incremented on incompatible changes). */
+#define RT_ABI_VERSION 1
+int rt_abi_version(void);
+
+/* Static description of a status code; never NULL. */
+const char *rt_status_string(int status);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char *rt_last_error(void);
+
+/* ---------------------------------------------------------------------
+ * Directions (sec. 2.1: HEALPix pixel centres, N_rays = 12 * 4^l with
+ * nside = 2^l; any nside >= 1 is accepted).
+ * ------------------------------------------------------------------- */
+
+/* Number of directions 12 * nside^2, or -1 if nside < 1 or nside > 2^20. */
+int64_t rt_healpix_npix(int nside);
+
+/* Writes the HEALPix RING-order pixel centres as unit vectors to host
+ * memory dirs_out[npix][3] (rings from the north pole, azimuth ascending).
+ * Errors: RT_ERR_ARG (bad nside, null pointer). */
+int rt_healpix_dirs(int nside, double *dirs_out);
+
+/* ---------------------------------------------------------------------
+ * Contribution grid: the leaf-only linear octree (sec. 2.3.1).
+ * ------------------------------------------------------------------- */
+
+/* Device bytes that rt_build_octree needs for n_leaves leaves at depth
+ * max_depth; 0 if the arguments are invalid. */
+size_t rt_octree_workspace_bytes(int64_t n_leaves, int max_depth);
+
+/* Validates a leaf-only linear octree and stages its search structures in
+ * the caller's device workspace.
+ *   keys[n_leaves]   host, Morton keys of the leaves' minimum corners,
+ *                    strictly increasing;
+ *   levels[n_leaves] host, refinement level of each leaf (0..max_depth);
+ *   max_depth        D, 1..21;
+ *   d_workspace      device, >= rt_octree_workspace_bytes(n, D) bytes,
+ *                    256-byte aligned; must stay allocated and unmodified
+ *                    while the handle is used;
+ *   stream           the upload is queued on it (the host arrays may be
+ *                    reused as soon as the call returns).
+ * The leaf values are not part of the octree: they are passed to every
+ * rt_columns call (so values can change without rebuilding).
+ * Errors: RT_ERR_ARG, RT_ERR_UNSORTED, RT_ERR_TILING (key[0] != 0, a key not
+ * aligned to its leaf's span, a gap or overlap key[i] + 8^(D-level[i]) !=
+ * key[i+1], or a last leaf not ending at 8^D), RT_ERR_WORKSPACE,
+ * RT_ERR_DEVICE.  On success *out receives a handle to free with
+ * rt_octree_free. */
+int rt_build_octree(const uint64_t *keys, const uint8_t *levels, int64_t n_leaves,
+                    int max_depth, void *d_workspace, size_t workspace_bytes, void *stream,
+                    rt_octree **out);
+
+/* Releases the host handle (the workspace stays the caller's). NULL is ok. */
+void rt_octree_free(rt_octree *tree);
+
+/* Leaf count and depth of a built octree (-1 for NULL). */
+int64_t rt_octree_leaves(const rt_octree *tree);
+int rt_octree_depth(const rt_octree *tree);
+
+/* ---------------------------------------------------------------------
+ * Column densities (sec. 2.3: I(p,q) = sum_k f_k r_k with f = rho).
+ * ------------------------------------------------------------------- */
+
+/* Forward walk of every ray (s, d), s < n_src, d < n_dirs.
+ *   d_rho    device, [n_leaves] leaf values, f64 for RT_FP64 and f32 for
+ *            RT_FP32_KAHAN; finite and >= 0 (not checked);
+ *   d_src    device, f64 [n_src][3] source points, each in [0,1)^3;
+ *   d_dirs   device, f64 [n_dirs][3] ray directions (finite, not all zero;
+ *            HEALPix unit vectors in the usual case);
+ *   kappa    attenuation coefficient for A = exp(-kappa N);
+ *   d_N      device output, N of ray (s, d) at d_N[s*stride_src + d*stride_dir]
+ *            (f64 or f32 per precision);
+ *   d_A      device output or NULL, A at the same offsets;
+ * The layout stride_src = 1, stride_dir = n_src (direction-major) gives
+ * coalesced stores.  A ray whose source lies outside [0,1)^3 or whose
+ * direction is invalid yields N = A = NaN (no other effect).
+ * Errors: RT_ERR_ARG (null pointers, n_src < 1, n_dirs < 1, n_src*n_dirs
+ * overflow, bad precision, negative strides), RT_ERR_DEVICE. */
+int rt_columns(const rt_octree *tree, const void *d_rho, int precision, const double *d_src,
+               int64_t n_src, const double *d_dirs, int64_t n_dirs, double kappa, void *d_N,
+               void *d_A, int64_t stride_src, int64_t stride_dir, void *stream);
+
+/* Adjoint of rt_columns for a loss L(N, A): re-walks the same rays and
+ * scatters g * l into the leaf gradient, where for each ray
+ *     g = dL/dN - kappa * A * dL/dA      (A = exp(-kappa N)),
+ * i.e. d_grad_rho[k] += sum over rays of g * r_k (N is linear in rho).
+ *   d_gN     device f32, dL/dN at the rt_columns offsets, or NULL (= 0);
+ *   d_gA     device f32, dL/dA, or NULL (= 0);
+ *   d_A      device f32, the A of the forward call; required iff d_gA;
+ *   d_grad_rho device f32 [n_leaves], accumulated with atomic adds (the
+ *            caller zeroes it); the summation order is not deterministic.
+ * The traversal is the FP64 one of rt_columns; g * r is formed in FP32.
+ * Errors: RT_ERR_ARG, RT_ERR_DEVICE. */
+int rt_columns_backward(const rt_octree *tree, const double *d_src, int64_t n_src,
+                        const double *d_dirs, int64_t n_dirs, double kappa, const float *d_gN,
+                        const float *d_gA, const float *d_A, int64_t stride_src,
+                        int64_t stride_dir, float *d_grad_rho, void *stream);
+
+/* Traversal record of every ray, for verification: the number of leaves
+ * visited and a 64-bit FNV-1a-style hash of the visited leaf indices
+ * (h = 0xcbf29ce484222325; per leaf index i: h = (h ^ i) * 0x100000001b3 mod
+ * 2^64), written at the rt_columns offsets to d_steps (int32) and d_hash
+ * (uint64).  In addition, for the n_sample rays listed in d_sample (device
+ * int64 ray ids r = d * n_src + s), the first cap visited leaf indices go to
+ * d_visited[j * cap ...] (int32, -1 after the end).  d_sample / d_visited may
+ * be NULL when n_sample is 0.  Errors: RT_ERR_ARG, RT_ERR_DEVICE. */
+int rt_columns_trace(const rt_octree *tree, const double *d_src, int64_t n_src,
+                     const double *d_dirs, int64_t n_dirs, int32_t *d_steps, uint64_t *d_hash,
+                     int64_t stride_src, int64_t stride_dir, const int64_t *d_sample,
+                     int64_t n_sample, int32_t *d_visited, int64_t cap, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RAYTHEIA_H */

@@ -303,6 +303,7 @@ int orc_columns(const uint64_t *keys, const uint8_t *levels, const double *rho,
                 if (status == ORC_OK) status = st;
                 o.N = NAN;
                 o.N32 = NAN;
+                o.steps = -1;
             }
             clamps += o.clamps;
             if (N64) N64[r] = o.N;

@@ -1,0 +1,24 @@
+"""MI355X reverse ray walk through a leaf-only linear octree.
+
+Column densities N = sum_k rho_k r_k and attenuations exp(-kappa N) for every
+(source point, HEALPix direction) pair, computed by hand-written HIP kernels
+for gfx950 behind the C ABI of include/raytheia.h (method: Zhu et al.,
+RAYTHEIA, sec. 2).  ``_abi`` is the ctypes binding of that ABI; ``raywalk``
+passes torch device tensors and the current stream to it.
+"""
+
+from . import _abi
+from .raywalk import (Octree, RayColumns, columns, columns_backward, columns_trace, healpix_dirs,
+                      healpix_npix, ray_columns)
+
+__all__ = [
+    "_abi",
+    "Octree",
+    "RayColumns",
+    "columns",
+    "columns_backward",
+    "columns_trace",
+    "healpix_dirs",
+    "healpix_npix",
+    "ray_columns",
+]

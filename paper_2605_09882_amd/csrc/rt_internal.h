@@ -1,0 +1,49 @@
+// Internal interface between the C ABI (rt_abi.cpp) and the HIP kernels
+// (rt_walk.hip).  Not installed; the public interface is include/raytheia.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace rt {
+
+// Device view of a built octree.  keys holds n+1 entries: the n leaf keys
+// and a sentinel 8^D, narrowed to 32 bits when D <= 10.  top[c] for the
+// 8^top_level cells c of level top_level is the index of the leaf holding the
+// cell's first finest cell; top[8^top_level] = n.  The leaf holding key k is
+// then found in [top[c], top[c+1]] with c = k >> 3 (D - top_level).
+struct TreeView {
+    const void *keys;
+    const uint32_t *top;
+    int64_t n;
+    int depth;
+    int top_level;
+    int wide_keys;  // 0: uint32_t keys, 1: uint64_t keys
+};
+
+// Rays (s, d) for s < n_src, d < n_dirs; outputs at s*stride_src + d*stride_dir.
+struct RayBatch {
+    const double *src;
+    int64_t n_src;
+    const double *dirs;
+    int64_t n_dirs;
+    int64_t stride_src;
+    int64_t stride_dir;
+};
+
+// Deepest level of the top table (bounded by the tree depth and by the
+// table size kept in shared memory).
+int top_table_level(int depth);
+
+hipError_t launch_forward(const TreeView &tree, const RayBatch &rays, const void *rho,
+                          int precision, double kappa, void *N, void *A, hipStream_t stream);
+
+hipError_t launch_backward(const TreeView &tree, const RayBatch &rays, double kappa,
+                           const float *gN, const float *gA, const float *A, float *grad,
+                           hipStream_t stream);
+
+hipError_t launch_trace(const TreeView &tree, const RayBatch &rays, int32_t *steps,
+                        uint64_t *hash, const int64_t *sample, int64_t n_sample,
+                        int32_t *visited, int64_t cap, hipStream_t stream);
+
+}  // namespace rt

@@ -1,0 +1,194 @@
+"""Torch-facing binding of the reverse ray-walk library.
+
+PyTorch supplies device memory and the current HIP stream; every step of the
+walk runs in the library's HIP kernels.  Outputs are [S, Dn] views over
+direction-major [Dn, S] buffers (stride_src = 1, stride_dir = S), the layout
+with coalesced stores.
+
+The adjoint follows from N being linear in rho: dN(s,d)/drho_k is the chord
+of ray (s, d) in leaf k (sec. 2.3: I = sum_k f_k r_k), so
+dL/drho_k = sum over rays of g * r_k with g = dL/dN - kappa A dL/dA.
+"""
+
+import numpy as np
+import torch
+
+from . import _abi
+
+_PREC = {torch.float64: _abi.RT_FP64, torch.float32: _abi.RT_FP32_KAHAN}
+
+
+def _stream(device):
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+def _ptr(t):
+    return None if t is None else t.data_ptr()
+
+
+def healpix_npix(nside):
+    return _abi.rt_healpix_npix(nside)
+
+
+def healpix_dirs(nside):
+    """HEALPix RING pixel centres as a host float64 array [12 nside^2, 3]."""
+    n = _abi.rt_healpix_npix(nside)
+    if n < 0:
+        raise ValueError(f"nside {nside} out of range")
+    out = np.empty((n, 3), dtype=np.float64)
+    _abi.rt_healpix_dirs(nside, out.ctypes.data)
+    return out
+
+
+class Octree:
+    """A validated leaf-only linear octree staged on one GPU.
+
+    keys (uint64) and levels (uint8) are host arrays describing the leaves;
+    the leaf values are not stored here: they go with every walk call.  The
+    device workspace is a torch tensor owned by this object.
+    """
+
+    def __init__(self, keys, levels, depth, device="cuda"):
+        keys = np.ascontiguousarray(keys, dtype=np.uint64)
+        levels = np.ascontiguousarray(levels, dtype=np.uint8)
+        if keys.shape != levels.shape or keys.ndim != 1:
+            raise ValueError("keys and levels must be 1-D arrays of equal length")
+        self.n = int(keys.shape[0])
+        self.depth = int(depth)
+        self.device = torch.device(device)
+        nbytes = _abi.rt_octree_workspace_bytes(self.n, self.depth)
+        if nbytes == 0:
+            raise ValueError(f"invalid octree size n={self.n} depth={self.depth}")
+        # 256 extra bytes so that the workspace can start on a 256-byte boundary
+        self._ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        base = self._ws.data_ptr()
+        off = (-base) % 256
+        self._handle = None
+        with torch.cuda.device(self.device):
+            self._handle = _abi.rt_build_octree(keys.ctypes.data, levels.ctypes.data, self.n,
+                                                self.depth, base + off, nbytes,
+                                                _stream(self.device))
+
+    @property
+    def handle(self):
+        return self._handle
+
+    def __del__(self, _free=_abi.rt_octree_free):
+        h = getattr(self, "_handle", None)
+        if h:
+            self._handle = None
+            try:
+                _free(h)
+            except Exception:  # interpreter shutdown: the library may be gone
+                pass
+
+
+def _as_dev(x, dtype, device, shape_last=None):
+    if not torch.is_tensor(x):
+        x = torch.as_tensor(np.ascontiguousarray(x))
+    x = x.to(device=device, dtype=dtype).contiguous()
+    if shape_last is not None and (x.ndim != 2 or x.shape[1] != shape_last):
+        raise ValueError(f"expected an [n, {shape_last}] array, got {tuple(x.shape)}")
+    return x
+
+
+def columns(tree, rho, src, dirs, kappa=1.0, with_A=True):
+    """N (and A = exp(-kappa N)) for every (source, direction).
+
+    rho: device tensor [n_leaves], float64 (FP64 walk) or float32 (FP32
+    walk with Kahan-compensated sums); src [S, 3] and dirs [Dn, 3] float64.
+    Returns (N, A) as [S, Dn] views (A is None unless with_A)."""
+    if rho.dtype not in _PREC:
+        raise TypeError("rho must be float64 or float32")
+    if not rho.is_cuda or rho.numel() != tree.n or not rho.is_contiguous():
+        raise ValueError("rho must be a contiguous device tensor with one value per leaf")
+    dev = tree.device
+    src = _as_dev(src, torch.float64, dev, 3)
+    dirs = _as_dev(dirs, torch.float64, dev, 3)
+    S, Dn = src.shape[0], dirs.shape[0]
+    N = torch.empty((Dn, S), dtype=rho.dtype, device=dev)
+    A = torch.empty((Dn, S), dtype=rho.dtype, device=dev) if with_A else None
+    _abi.rt_columns(tree.handle, rho.data_ptr(), _PREC[rho.dtype], src.data_ptr(), S,
+                    dirs.data_ptr(), Dn, kappa, N.data_ptr(), _ptr(A), 1, S, _stream(dev))
+    return N.t(), (A.t() if A is not None else None)
+
+
+def _dir_major_f32(x, S, Dn, dev):
+    """x as float32 with strides (1, S) over a [Dn, S] buffer (or None)."""
+    if x is None:
+        return None
+    x = x.to(device=dev, dtype=torch.float32)
+    if x.shape != (S, Dn):
+        raise ValueError(f"gradient shape {tuple(x.shape)} != {(S, Dn)}")
+    if x.stride() == (1, S):
+        return x
+    return x.t().contiguous().t()
+
+
+def columns_backward(tree, src, dirs, kappa, gN=None, gA=None, A=None, grad=None):
+    """Adds dL/drho (float32, [n_leaves]) into grad (created zeroed if None)."""
+    dev = tree.device
+    src = _as_dev(src, torch.float64, dev, 3)
+    dirs = _as_dev(dirs, torch.float64, dev, 3)
+    S, Dn = src.shape[0], dirs.shape[0]
+    gN = _dir_major_f32(gN, S, Dn, dev)
+    gA = _dir_major_f32(gA, S, Dn, dev)
+    A = _dir_major_f32(A, S, Dn, dev) if gA is not None else None
+    if grad is None:
+        grad = torch.zeros(tree.n, dtype=torch.float32, device=dev)
+    elif grad.dtype != torch.float32 or grad.numel() != tree.n or not grad.is_contiguous():
+        raise ValueError("grad must be a contiguous float32 tensor with one value per leaf")
+    _abi.rt_columns_backward(tree.handle, src.data_ptr(), S, dirs.data_ptr(), Dn, kappa,
+                             _ptr(gN), _ptr(gA), _ptr(A), 1, S, grad.data_ptr(), _stream(dev))
+    return grad
+
+
+def columns_trace(tree, src, dirs, sample=None, cap=0):
+    """Per ray: leaves visited (int32) and the FNV hash of their indices
+    (int64 holding the uint64 bits), as [S, Dn] views; plus, for the ray ids
+    in sample (r = d * S + s), the first cap visited leaf indices."""
+    dev = tree.device
+    src = _as_dev(src, torch.float64, dev, 3)
+    dirs = _as_dev(dirs, torch.float64, dev, 3)
+    S, Dn = src.shape[0], dirs.shape[0]
+    steps = torch.empty((Dn, S), dtype=torch.int32, device=dev)
+    h = torch.empty((Dn, S), dtype=torch.int64, device=dev)
+    visited = None
+    n_sample = 0
+    sp = None
+    if sample is not None and len(sample) > 0:
+        sample = torch.as_tensor(np.asarray(sample, dtype=np.int64)).to(dev)
+        n_sample = int(sample.numel())
+        visited = torch.empty((n_sample, cap), dtype=torch.int32, device=dev)
+        sp = sample.data_ptr()
+    _abi.rt_columns_trace(tree.handle, src.data_ptr(), S, dirs.data_ptr(), Dn, steps.data_ptr(),
+                          h.data_ptr(), 1, S, sp, n_sample, _ptr(visited), cap, _stream(dev))
+    return steps.t(), h.t(), visited
+
+
+class RayColumns(torch.autograd.Function):
+    """(N, A) = RayColumns.apply(rho, tree, src, dirs, kappa), differentiable
+    in rho through the library's adjoint walk."""
+
+    @staticmethod
+    def forward(ctx, rho, tree, src, dirs, kappa):
+        dev = tree.device
+        src = _as_dev(src, torch.float64, dev, 3)
+        dirs = _as_dev(dirs, torch.float64, dev, 3)
+        N, A = columns(tree, rho.detach(), src, dirs, kappa, with_A=True)
+        ctx.tree = tree
+        ctx.kappa = kappa
+        ctx.rho_dtype = rho.dtype
+        ctx.save_for_backward(src, dirs, A)
+        return N, A
+
+    @staticmethod
+    def backward(ctx, gN, gA):
+        src, dirs, A = ctx.saved_tensors
+        grad = columns_backward(ctx.tree, src, dirs, ctx.kappa, gN=gN, gA=gA, A=A)
+        return grad.to(ctx.rho_dtype), None, None, None, None
+
+
+def ray_columns(rho, tree, src, dirs, kappa=1.0):
+    """Differentiable (N, A); see RayColumns."""
+    return RayColumns.apply(rho, tree, src, dirs, kappa)

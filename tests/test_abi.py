@@ -1,0 +1,122 @@
+"""Host side of the C ABI (no GPU needed): the library loads, exports every
+symbol the header declares, validates its arguments before touching the
+device, and its HEALPix table matches the oracle's."""
+
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2605_09882_amd import _abi
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "raytheia.h")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return _abi.load()
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(rt_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_exports_every_declared_symbol(lib):
+    names = declared_functions()
+    assert len(names) >= 13
+    for n in names:
+        assert hasattr(lib, n), n
+    assert sorted(names) == sorted(_abi.EXPORTS)
+
+
+def test_version_and_status_strings(lib):
+    assert _abi.rt_abi_version() == 1
+    for st in (0, -1, -2, -3, -4, -5, -6):
+        assert _abi.rt_status_string(st) not in ("", "unknown status")
+    assert _abi.rt_status_string(-99) == "unknown status"
+
+
+def test_healpix_npix(lib):
+    assert [_abi.rt_healpix_npix(n) for n in (1, 2, 4, 8)] == [12, 48, 192, 768]
+    assert _abi.rt_healpix_npix(0) == -1
+    assert _abi.rt_healpix_npix(-3) == -1
+    assert _abi.rt_healpix_npix((1 << 20) + 1) == -1
+
+
+@pytest.mark.parametrize("nside", [1, 2, 3, 4, 8, 16, 64])
+def test_healpix_matches_oracle(orc, nside):
+    import paper_2605_09882_amd as rt
+    mine = rt.healpix_dirs(nside)
+    ref = orc.healpix_ring(nside)
+    assert mine.shape == ref.shape
+    assert np.abs(mine - ref).max() <= 1e-15
+
+
+def test_healpix_errors(lib):
+    out = np.empty((12, 3))
+    assert lib.rt_healpix_dirs(0, out.ctypes.data) == _abi.RT_ERR_ARG
+    assert b"nside" in lib.rt_last_error()
+    assert lib.rt_healpix_dirs(1, None) == _abi.RT_ERR_ARG
+
+
+def test_workspace_bytes(lib):
+    assert _abi.rt_octree_workspace_bytes(0, 5) == 0
+    assert _abi.rt_octree_workspace_bytes(10, 0) == 0
+    assert _abi.rt_octree_workspace_bytes(10, 22) == 0
+    small = _abi.rt_octree_workspace_bytes(8, 1)
+    assert small > 0 and small % 256 == 0
+    # 64-bit keys beyond depth 10
+    assert _abi.rt_octree_workspace_bytes(1000, 11) > _abi.rt_octree_workspace_bytes(1000, 10)
+
+
+def _build(lib, keys, levels, depth, ws=None, nbytes=None):
+    keys = np.ascontiguousarray(keys, dtype=np.uint64)
+    levels = np.ascontiguousarray(levels, dtype=np.uint8)
+    h = ctypes.c_void_p()
+    st = lib.rt_build_octree(keys.ctypes.data, levels.ctypes.data, len(keys), depth, ws,
+                             nbytes or 0, None, ctypes.byref(h))
+    return st, h
+
+
+def test_build_rejects_bad_trees_before_device_work(lib):
+    import workloads as W
+    t = W.random_octree(4, 0.4, 11, min_level=1)
+    k, L = t.keys.copy(), t.levels.copy()
+    k[[3, 4]] = k[[4, 3]]
+    L[[3, 4]] = L[[4, 3]]
+    assert _build(lib, k, L, 4)[0] == _abi.RT_ERR_UNSORTED
+    assert _build(lib, np.delete(t.keys, 5), np.delete(t.levels, 5), 4)[0] == _abi.RT_ERR_TILING
+    L = t.levels.copy()
+    L[int(np.nonzero(t.levels == 4)[0][1])] = 3
+    assert _build(lib, t.keys, L, 4)[0] == _abi.RT_ERR_TILING
+    k = t.keys.copy()
+    k[int(np.nonzero(t.levels <= 3)[0][2])] += np.uint64(1)
+    assert _build(lib, k, t.levels, 4)[0] in (_abi.RT_ERR_TILING, _abi.RT_ERR_UNSORTED)
+    assert _build(lib, t.keys[:-1], t.levels[:-1], 4)[0] == _abi.RT_ERR_TILING
+    assert _build(lib, t.keys, t.levels, 0)[0] == _abi.RT_ERR_ARG
+    assert _build(lib, t.keys, t.levels, 22)[0] == _abi.RT_ERR_ARG
+    # valid tree, bad workspace: rejected on the host
+    assert _build(lib, t.keys, t.levels, 4, None, 0)[0] == _abi.RT_ERR_WORKSPACE
+    assert _build(lib, t.keys, t.levels, 4, 0x1001, 1 << 20)[0] == _abi.RT_ERR_WORKSPACE
+    assert _build(lib, t.keys, t.levels, 4, 0x100000, 16)[0] == _abi.RT_ERR_WORKSPACE
+    # null arrays and output
+    h = ctypes.c_void_p()
+    assert lib.rt_build_octree(None, None, 5, 4, None, 0, None, ctypes.byref(h)) == _abi.RT_ERR_ARG
+    assert lib.rt_build_octree(t.keys.ctypes.data, t.levels.ctypes.data, len(t.keys), 4, None, 0,
+                               None, None) == _abi.RT_ERR_ARG
+
+
+def test_walk_calls_reject_null_handles(lib):
+    assert lib.rt_columns(None, 1, 0, 1, 1, 1, 1, 1.0, 1, None, 1, 1, None) == _abi.RT_ERR_ARG
+    assert lib.rt_columns_backward(None, 1, 1, 1, 1, 1.0, 1, None, None, 1, 1, 1, None) == \
+        _abi.RT_ERR_ARG
+    assert lib.rt_columns_trace(None, 1, 1, 1, 1, 1, 1, 1, 1, None, 0, None, 0, None) == \
+        _abi.RT_ERR_ARG
+    assert lib.rt_octree_leaves(None) == -1
+    assert lib.rt_octree_depth(None) == -1
+    lib.rt_octree_free(None)

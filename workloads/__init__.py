@@ -21,6 +21,7 @@ from .octree import (
     threshold_refined_octree,
     uniformity_merged_octree,
     random_octree,
+    sparse_random_octree,
     split_leaf,
 )
 from .sources import cell_centres, leaf_centres, density_weighted_points, random_points
@@ -38,6 +39,7 @@ __all__ = [
     "threshold_refined_octree",
     "uniformity_merged_octree",
     "random_octree",
+    "sparse_random_octree",
     "split_leaf",
     "cell_centres",
     "leaf_centres",

@@ -228,3 +228,32 @@ def split_leaf(tree, i):
     levels = np.concatenate([tree.levels[:i], np.full(8, L + 1, dtype=np.uint8), tree.levels[i + 1:]])
     rho = np.concatenate([tree.rho[:i], np.full(8, tree.rho[i]), tree.rho[i + 1:]])
     return Octree(tree.depth, keys, levels, rho, dict(tree.info))
+
+
+def sparse_random_octree(depth, n_splits, seed, focus=None):
+    """Deep trees without a dense grid: starting from the root, n_splits
+    times pick a random leaf above the maximum depth (or, with focus = a
+    point in [0,1)^3, the leaf holding that point) and split it into its
+    eight children.  Values are lognormal."""
+    rng = np.random.default_rng(seed)
+    leaves = {0: 0}  # key -> level
+    for _ in range(n_splits):
+        if focus is not None:
+            cell = [int(np.floor(f * (1 << depth))) for f in focus]
+            k = int(morton_encode(cell[0], cell[1], cell[2], depth))
+            key = max(kk for kk in leaves if kk <= k)
+        else:
+            cand = [kk for kk, L in leaves.items() if L < depth]
+            if not cand:
+                break
+            key = cand[int(rng.integers(len(cand)))]
+        L = leaves[key]
+        if L >= depth:
+            continue
+        span = 8 ** (depth - L - 1)
+        for c in range(8):
+            leaves[key + c * span] = L + 1
+    keys = np.array(sorted(leaves), dtype=np.uint64)
+    levels = np.array([leaves[int(k)] for k in keys], dtype=np.uint8)
+    rho = np.exp(rng.standard_normal(len(keys)))
+    return Octree(depth, keys, levels, rho, {"rule": "sparse_random", "seed": seed})

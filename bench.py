@@ -1,0 +1,239 @@
+"""Benchmark of the reverse ray walk on one MI355X.
+
+Workload (default): the paper-scale cloud -- a 512^3 lognormal field with a
+k^-4 spectrum and sigma_ln(rho) = 2, coarsened to a leaf-only octree by the
+density + uniformity rule (about 39M leaves), rays from all 512^3 cell
+centres in the 12 HEALPix directions (nside = 1), about 1.6e9 rays.
+
+One step = one pass of the whole hot path over that batch: the HEALPix
+direction table, the FP32-Kahan forward walk (N and A = exp(-kappa N)), and
+the adjoint walk of L = sum w A (w ~ U(0,1) per ray) scattering dL/drho onto
+the leaves.  The value is ray-leaf steps per second of that pass: the leaf
+visits of the forward walk (the adjoint re-walks the same ones) divided by
+the time of the pass.  The FP64 walk over the same rays is timed after the
+pass and reported beside it.
+
+Prints one JSON line.  --gpus N > 1 is refused: this build runs on one GPU.
+"""
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+CPU_SAMPLE_STRIDE = 4096
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=5)
+    p.add_argument("--warmup", type=int, default=1)
+    p.add_argument("--workload", type=int, default=4, help="workload index (0..4)")
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--no-fp64", action="store_true")
+    return p.parse_args()
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("rt_walk.hip", "rt_abi.cpp", "rt_internal.h"):
+        with open(os.path.join(ROOT, "paper_2605_09882_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def stored_traffic(kernel, workload, src_hash):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if
+    it was taken on the current kernel sources."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    e = rec.get(workload, {}).get(kernel)
+    if not e or e.get("source_hash") != src_hash:
+        return None
+    return e.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(w, dirs_host):
+    """The oracle, single-threaded, on every CPU_SAMPLE_STRIDE-th source."""
+    import numpy as np
+
+    import oracle
+
+    src = w.sources[::CPU_SAMPLE_STRIDE]
+    t0 = time.perf_counter()
+    out = oracle.columns(w.tree, src, dirs_host, w.kappa, rho32=w.tree.rho.astype(np.float32))
+    dt = time.perf_counter() - t0
+    steps = int(out["steps"].sum())
+    return {"value": steps / dt, "unit": "ray-leaf steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"every {CPU_SAMPLE_STRIDE}th source ({src.shape[0]} sources x "
+                      f"{dirs_host.shape[0]} dirs = {src.shape[0] * dirs_host.shape[0]} rays, "
+                      f"{steps} leaf steps, {dt:.1f} s, FP64 + FP32-Kahan columns)"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
+              "design is described but not built", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2605_09882_amd as rt
+    import workloads as W
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+
+    t0 = time.time()
+    w = W.make_workload(args.workload)
+    log(f"workload {w.name}: {w.tree.n} leaves, {w.sources.shape[0]} sources, nside {w.nside}, "
+        f"generated in {time.time() - t0:.1f} s")
+
+    tree = rt.Octree(w.tree.keys, w.tree.levels, w.tree.depth, dev)
+    src = torch.as_tensor(w.sources).to(dev)
+    rho32 = torch.as_tensor(w.tree.rho.astype(np.float32)).to(dev)
+    rho64 = torch.as_tensor(w.tree.rho).to(dev)
+    S = src.shape[0]
+    Dn = rt.healpix_npix(w.nside)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(3000 + w.index)
+    wgt = torch.rand((Dn, S), generator=gen, device=dev, dtype=torch.float32).t()
+    grad = torch.zeros(w.tree.n, dtype=torch.float32, device=dev)
+    kappa = w.kappa
+
+    dirs_host = rt.healpix_dirs(w.nside)
+    dirs = torch.as_tensor(dirs_host).to(dev)
+    steps_t, _, _ = rt.columns_trace(tree, src, dirs)
+    total_steps = int(steps_t.to(torch.int64).sum())
+    if int(steps_t.min()) < 1:
+        raise RuntimeError("a ray of the workload was rejected")
+    del steps_t
+    rays = S * Dn
+    log(f"{rays} rays, {total_steps} ray-leaf steps ({total_steps / rays:.1f} per ray)")
+
+    ev = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
+
+    def one_step(marks=None):
+        d = torch.as_tensor(rt.healpix_dirs(w.nside)).to(dev, non_blocking=False)
+        if marks:
+            marks[0].record()
+        N, A = rt.columns(tree, rho32, src, d, kappa)
+        if marks:
+            marks[1].record()
+        grad.zero_()
+        if marks:
+            marks[2].record()
+        rt.columns_backward(tree, src, d, kappa, gA=wgt, A=A, grad=grad)
+        if marks:
+            marks[3].record()
+        return N, A
+
+    for _ in range(args.warmup):
+        one_step()
+    torch.cuda.synchronize()
+
+    marks = [[ev() for _ in range(4)] for _ in range(args.steps)]
+    start, stop = ev(), ev()
+    torch.cuda.synchronize()
+    t_wall = time.perf_counter()
+    start.record()
+    for k in range(args.steps):
+        one_step(marks[k])
+    stop.record()
+    torch.cuda.synchronize()
+    t_wall = time.perf_counter() - t_wall
+    t_gpu = start.elapsed_time(stop) / 1e3
+    t_total = max(t_wall, t_gpu)
+    ms_step = 1e3 * t_total / args.steps
+    fwd_ms = float(np.mean([m[0].elapsed_time(m[1]) for m in marks]))
+    bwd_ms = float(np.mean([m[2].elapsed_time(m[3]) for m in marks]))
+    value = total_steps * args.steps / t_total
+    log(f"step {ms_step:.1f} ms: forward {fwd_ms:.1f} ms, adjoint {bwd_ms:.1f} ms")
+
+    # FP64 walk of the same rays, for comparison
+    fp64 = None
+    if not args.no_fp64:
+        rt.columns(tree, rho64, src, dirs, kappa)
+        torch.cuda.synchronize()
+        a, b = ev(), ev()
+        a.record()
+        for _ in range(args.steps):
+            N64, _ = rt.columns(tree, rho64, src, dirs, kappa)
+        b.record()
+        torch.cuda.synchronize()
+        ms64 = a.elapsed_time(b) / args.steps
+        fp64 = {"ms": round(ms64, 3), "steps_per_s": total_steps / (ms64 / 1e3),
+                "bytes_per_step": 12}
+        del N64
+        log(f"FP64 walk {ms64:.1f} ms")
+
+    # roofline of the dominant kernel (algorithmic bytes per launch / duration)
+    fwd_bytes = total_steps * 8 + rays * (24 + 4 + 4)
+    bwd_bytes = total_steps * (4 + 8) + rays * (24 + 4 + 4)
+    if bwd_ms >= fwd_ms:
+        kname, kms, kbytes = "k_backward", bwd_ms, bwd_bytes
+    else:
+        kname, kms, kbytes = "k_forward_f32k", fwd_ms, fwd_bytes
+    achieved = kbytes / (kms / 1e3) / 1e9
+    src_hash = kernel_source_hash()
+    traffic = stored_traffic(kname, w.name, src_hash)
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "kernel": kname, "kernel_ms": round(kms, 3), "algorithmic_bytes": kbytes}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(w, dirs_host)
+        log(f"cpu baseline {cpu['value']:.3e} steps/s ({cpu['sample']})")
+
+    line = {
+        "metric": "ray-leaf steps/sec (FP32-Kahan forward + adjoint pass; FP64 walk beside it)",
+        "value": value,
+        "unit": "ray-leaf steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 (Kahan) accumulation, f64 traversal",
+        "data": "synthetic",
+        "config": {"workload": w.name, "leaves": w.tree.n, "sources": S, "directions": Dn,
+                   "rays": rays, "ray_leaf_steps": total_steps, "kappa": kappa,
+                   "parallelism": "single GPU"},
+        "forward_ms": round(fwd_ms, 3),
+        "adjoint_ms": round(bwd_ms, 3),
+        "fp32k_forward_steps_per_s": total_steps / (fwd_ms / 1e3),
+        "adjoint_steps_per_s": total_steps / (bwd_ms / 1e3),
+        "fp64_walk": fp64,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "kernel_source_hash": src_hash,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

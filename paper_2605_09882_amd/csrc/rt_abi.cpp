@@ -39,12 +39,20 @@ int ok() {
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-// Bytes of the key copy and of the top table inside the workspace.
-void workspace_layout(int64_t n, int depth, size_t *key_bytes, size_t *top_bytes) {
+// Workspace layout: key copy (with sentinel), level copy, top table.
+struct Layout {
+    size_t keys, levels, top;
+    size_t total() const { return keys + levels + top; }
+};
+
+Layout workspace_layout(int64_t n, int depth) {
     const size_t ksize = depth <= 10 ? 4 : 8;
-    const int lt = rt::top_table_level(depth);
-    *key_bytes = align256(ksize * (size_t)(n + 1));
-    *top_bytes = align256(4 * (((size_t)1 << (3 * lt)) + 1));
+    const int lt = rt::top_table_level(depth, n);
+    Layout l;
+    l.keys = align256(ksize * (size_t)(n + 1));
+    l.levels = align256((size_t)n);
+    l.top = align256(4 * (((size_t)1 << (3 * lt)) + 1));
+    return l;
 }
 
 constexpr int64_t kMaxLeaves = ((int64_t)1 << 31) - 2;  // leaf indices are 32-bit
@@ -168,9 +176,7 @@ int rt_healpix_dirs(int nside, double *dirs_out) {
 
 size_t rt_octree_workspace_bytes(int64_t n_leaves, int max_depth) {
     if (n_leaves < 1 || n_leaves > kMaxLeaves || max_depth < 1 || max_depth > 21) return 0;
-    size_t kb, tb;
-    workspace_layout(n_leaves, max_depth, &kb, &tb);
-    return kb + tb;
+    return workspace_layout(n_leaves, max_depth).total();
 }
 
 int rt_build_octree(const uint64_t *keys, const uint8_t *levels, int64_t n_leaves, int max_depth,
@@ -201,13 +207,14 @@ int rt_build_octree(const uint64_t *keys, const uint8_t *levels, int64_t n_leave
 
     if (!d_workspace) return fail(RT_ERR_WORKSPACE, "null workspace");
     if (((uintptr_t)d_workspace & 255) != 0) return fail(RT_ERR_WORKSPACE, "workspace not 256-byte aligned");
-    size_t kb, tb;
-    workspace_layout(n_leaves, D, &kb, &tb);
-    if (workspace_bytes < kb + tb)
-        return fail(RT_ERR_WORKSPACE, "workspace has %zu bytes, needs %zu", workspace_bytes, kb + tb);
+    const Layout lay = workspace_layout(n_leaves, D);
+    const size_t kb = lay.keys, lb = lay.levels;
+    if (workspace_bytes < lay.total())
+        return fail(RT_ERR_WORKSPACE, "workspace has %zu bytes, needs %zu", workspace_bytes,
+                    lay.total());
 
-    // stage keys (+ sentinel) and the top table in one host buffer
-    std::vector<unsigned char> host(kb + tb, 0);
+    // stage keys (+ sentinel), levels and the top table in one host buffer
+    std::vector<unsigned char> host(lay.total(), 0);
     const bool wide = D > 10;
     if (wide) {
         uint64_t *k = reinterpret_cast<uint64_t *>(host.data());
@@ -218,10 +225,11 @@ int rt_build_octree(const uint64_t *keys, const uint8_t *levels, int64_t n_leave
         for (int64_t i = 0; i < n_leaves; ++i) k[i] = (uint32_t)keys[i];
         k[n_leaves] = (uint32_t)end;
     }
-    const int lt = rt::top_table_level(D);
+    std::memcpy(host.data() + kb, levels, (size_t)n_leaves);
+    const int lt = rt::top_table_level(D, n_leaves);
     const int64_t ncell = (int64_t)1 << (3 * lt);
     const int shift = 3 * (D - lt);
-    uint32_t *top = reinterpret_cast<uint32_t *>(host.data() + kb);
+    uint32_t *top = reinterpret_cast<uint32_t *>(host.data() + kb + lb);
     int64_t i = 0;
     for (int64_t c = 0; c < ncell; ++c) {
         const uint64_t base = (uint64_t)c << shift;
@@ -234,15 +242,17 @@ int rt_build_octree(const uint64_t *keys, const uint8_t *levels, int64_t n_leave
     hipError_t e = hipGetDevice(&device);
     if (e != hipSuccess) return device_status(e, "hipGetDevice");
     hipStream_t s = static_cast<hipStream_t>(stream);
-    e = hipMemcpyAsync(d_workspace, host.data(), kb + tb, hipMemcpyHostToDevice, s);
+    e = hipMemcpyAsync(d_workspace, host.data(), lay.total(), hipMemcpyHostToDevice, s);
     if (e != hipSuccess) return device_status(e, "hipMemcpyAsync(octree)");
     e = hipStreamSynchronize(s);  // the staging buffer dies with this call
     if (e != hipSuccess) return device_status(e, "hipStreamSynchronize");
 
     rt_octree *t = new (std::nothrow) rt_octree;
     if (!t) return fail(RT_ERR_ARG, "out of host memory");
-    t->view.keys = d_workspace;
-    t->view.top = reinterpret_cast<const uint32_t *>(static_cast<unsigned char *>(d_workspace) + kb);
+    unsigned char *base = static_cast<unsigned char *>(d_workspace);
+    t->view.keys = base;
+    t->view.levels = base + kb;
+    t->view.top = reinterpret_cast<const uint32_t *>(base + kb + lb);
     t->view.n = n_leaves;
     t->view.depth = D;
     t->view.top_level = lt;

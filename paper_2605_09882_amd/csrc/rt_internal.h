@@ -8,12 +8,14 @@
 namespace rt {
 
 // Device view of a built octree.  keys holds n+1 entries: the n leaf keys
-// and a sentinel 8^D, narrowed to 32 bits when D <= 10.  top[c] for the
+// and a sentinel 8^D, narrowed to 32 bits when D <= 10; levels the n leaf
+// levels.  top[c] for the
 // 8^top_level cells c of level top_level is the index of the leaf holding the
 // cell's first finest cell; top[8^top_level] = n.  The leaf holding key k is
 // then found in [top[c], top[c+1]] with c = k >> 3 (D - top_level).
 struct TreeView {
     const void *keys;
+    const uint8_t *levels;  // n refinement levels
     const uint32_t *top;
     int64_t n;
     int depth;
@@ -31,9 +33,8 @@ struct RayBatch {
     int64_t stride_dir;
 };
 
-// Deepest level of the top table (bounded by the tree depth and by the
-// table size kept in shared memory).
-int top_table_level(int depth);
+// Level of the top table for a tree of the given depth and leaf count.
+int top_table_level(int depth, int64_t n_leaves);
 
 hipError_t launch_forward(const TreeView &tree, const RayBatch &rays, const void *rho,
                           int precision, double kappa, void *N, void *A, hipStream_t stream);

@@ -7,20 +7,28 @@
 // their results to consecutive addresses when stride_src = 1.
 //
 // Walk of one ray (sec. 2.3.1 DDA + Morton lookup, sec. 2.3.2 slab chord),
-// the same step definition as the CPU reference, in FP64 with no
-// floating-point contraction (this file is compiled with -ffp-contract=off;
-// the one fused multiply-add of the position update is written as fma):
+// the step definition of the CPU reference, in FP64 and bit-identical to it:
 //   probe p = floor(Q 2^D) (integer finest cell);
 //   loop: k = Morton(p); i = leaf holding k (largest key <= k);
-//         edge = 2^(D - level), with 8^(D-level) = key[i+1] - key[i];
+//         edge = 2^(D - level_i);
 //         anchor = p rounded down to the edge;
 //         far-plane times tf_a = (plane_a h - Q_a) / m_a for bounding axes
-//         (1/m_a finite), taken from a per-ray reciprocal;
+//         (1/m_a finite), +inf for the others;
 //         t_out = min(tf_x, tf_y, tf_z) in that order;
 //         l = t_out - t_in (clamped at 0), accumulate rho_i l;
 //         axes with tf_a == t_out step to the neighbour cell, the others
 //         take floor(fma(m_a, t_out, Q_a) 2^D) clamped to the leaf;
 //         stop when p leaves [0, 2^D)^3.
+// The kernel evaluates the same roundings with fewer operations: with
+// Qs = Q 2^D, ms = m 2^D and ih = (1/m) 2^-D (exact power-of-two scalings),
+//   (plane h - Q) (1/m) == (plane - Qs) ih   and
+//   fma(m, t, Q) 2^D   == fma(ms, t, Qs)
+// hold bit for bit, because scaling by a power of two commutes with
+// rounding (no operand here is subnormal or overflows for directions with
+// |m_a| <= 2^1000).  Non-bounding axes get ih = +inf and the upper face as
+// plane (which lies strictly above Qs), so their far time is +inf without a
+// select.  This file is compiled with -ffp-contract=off: every FP operation
+// rounds as written.
 #include "rt_internal.h"
 
 #include <hip/hip_runtime.h>
@@ -32,7 +40,16 @@ namespace rt {
 namespace {
 
 constexpr int kBlock = 256;
-constexpr int kTopLevelMax = 7;  // 8^7 + 1 entries = 8 MB of table at most
+constexpr int kWaves = kBlock / 64;
+constexpr int kTopLevelMax = 9;     // at most 8^9 + 1 table entries (512 MB)
+constexpr int kLutBits = 10;        // Morton spread table covers depths <= 10
+
+// Adjoint scatter aggregation: per wavefront, a direct-mapped table in LDS
+// of (leaf, partial dL/drho) pairs, flushed to global memory every
+// kFlushEvery steps of the wavefront and at its end.
+constexpr int kAggSlots = 512;
+constexpr int kFlushEvery = 16;
+constexpr uint32_t kEmpty = 0xffffffffu;
 
 // ---------------------------------------------------------------------
 // Morton keys: spread the bits of each coordinate three apart.
@@ -57,38 +74,45 @@ __device__ __forceinline__ uint64_t spread21(uint64_t x) {
     return x;
 }
 
-template <typename KeyT>
-__device__ __forceinline__ KeyT morton(int x, int y, int z);
-
-template <>
-__device__ __forceinline__ uint32_t morton<uint32_t>(int x, int y, int z) {
-    return spread10((uint32_t)x) | (spread10((uint32_t)y) << 1) | (spread10((uint32_t)z) << 2);
+// 32-bit keys (depth <= 10) read the spread bits from a table in LDS.
+__device__ __forceinline__ uint32_t morton(const uint32_t *lut, int x, int y, int z, uint32_t) {
+    return lut[x] | (lut[y] << 1) | (lut[z] << 2);
 }
 
-template <>
-__device__ __forceinline__ uint64_t morton<uint64_t>(int x, int y, int z) {
+__device__ __forceinline__ uint64_t morton(const uint32_t *, int x, int y, int z, uint64_t) {
     return spread21((uint64_t)x) | (spread21((uint64_t)y) << 1) | (spread21((uint64_t)z) << 2);
 }
 
-__device__ __forceinline__ int ctz_key(uint32_t v) { return __builtin_ctz(v); }
-__device__ __forceinline__ int ctz_key(uint64_t v) { return __builtin_ctzll(v); }
-
 template <typename KeyT>
 struct Tree {
-    const KeyT *__restrict__ keys;     // n + 1 keys (sentinel 8^D last)
-    const uint32_t *__restrict__ top;  // 8^top_level + 1 leaf indices
+    const KeyT *__restrict__ keys;      // n + 1 keys (sentinel 8^D last)
+    const uint8_t *__restrict__ levels;  // n leaf levels
+    const uint32_t *__restrict__ top;   // 8^top_level + 1 leaf indices
     int depth;
     int top_shift;  // 3 * (depth - top_level)
 };
 
-// Largest leaf index i with keys[i] <= k.  The top table narrows the range
-// to the leaves that meet the level-top_level cell of k; the rest is a
-// binary search in the sorted keys.
+// Fills the block's Morton spread table (32-bit keys only); all threads of
+// the block must call it.
+template <typename KeyT>
+__device__ __forceinline__ void init_lut(uint32_t *lut, int depth) {
+    if (sizeof(KeyT) == 4) {
+        for (int j = threadIdx.x; j < (1 << depth); j += blockDim.x) lut[j] = spread10((uint32_t)j);
+    }
+    __syncthreads();
+}
+
+// Largest leaf index i with keys[i] <= k.  top[c] is the leaf holding the
+// first finest cell of the level-top_level cell c.  If top[c] == top[c+1]
+// that leaf covers all of cell c; otherwise the leaves of cell c are exactly
+// top[c] .. top[c+1]-1 (a leaf starting before the next cell's first key
+// and reaching into it would be coarser than the cell and cover all of it).
 template <typename KeyT>
 __device__ __forceinline__ uint32_t find_leaf(const Tree<KeyT> &t, KeyT k) {
     const uint32_t c = (uint32_t)(k >> t.top_shift);
     uint32_t lo = t.top[c];
-    uint32_t hi = t.top[c + 1] + 1u;
+    const uint32_t nx = t.top[c + 1];
+    uint32_t hi = nx == lo ? lo + 1u : nx;
     while (hi - lo > 1u) {
         const uint32_t mid = (lo + hi) >> 1;
         if (t.keys[mid] <= k)
@@ -100,85 +124,121 @@ __device__ __forceinline__ uint32_t find_leaf(const Tree<KeyT> &t, KeyT k) {
 }
 
 // ---------------------------------------------------------------------
-// The walk.  Visitor::step(leaf, l) is called once per visited leaf, in
-// order.  Returns the number of leaves visited, or -1 for an invalid ray
-// (source outside [0,1)^3, non-finite or all-zero direction, or a walk
-// longer than the 3 * 2^D + 3 steps a valid ray can take).
+// State of one ray and one step of its walk
 // ---------------------------------------------------------------------
 
+struct Ray {
+    double qx, qy, qz;  // Q 2^D
+    double mx, my, mz;  // m 2^D
+    double ix, iy, iz;  // (1/m) 2^-D, +inf for non-bounding axes
+    bool ux, uy, uz;    // far plane is the upper face (m > 0, or non-bounding)
+    int cx, cy, cz;     // probe cell
+    double t_in;
+    int steps;
+};
+
+// Sets up the ray; false for an invalid ray (source outside [0,1)^3,
+// non-finite direction, or no bounding axis).
+__device__ __forceinline__ bool ray_init(Ray &r, int depth, const double *q, const double *m) {
+    const double scale = (double)(1 << depth);  // 2^D
+    const double h = 1.0 / scale;               // 2^-D
+    const double Qx = q[0], Qy = q[1], Qz = q[2];
+    const double Mx = m[0], My = m[1], Mz = m[2];
+    if (!(Qx >= 0.0 && Qx < 1.0 && Qy >= 0.0 && Qy < 1.0 && Qz >= 0.0 && Qz < 1.0)) return false;
+    if (!(isfinite(Mx) && isfinite(My) && isfinite(Mz))) return false;
+    const double inx = 1.0 / Mx, iny = 1.0 / My, inz = 1.0 / Mz;
+    const bool bx = isfinite(inx), by = isfinite(iny), bz = isfinite(inz);
+    if (!(bx || by || bz)) return false;
+    r.qx = Qx * scale;
+    r.qy = Qy * scale;
+    r.qz = Qz * scale;
+    r.mx = Mx * scale;
+    r.my = My * scale;
+    r.mz = Mz * scale;
+    r.ix = bx ? inx * h : (double)INFINITY;
+    r.iy = by ? iny * h : (double)INFINITY;
+    r.iz = bz ? inz * h : (double)INFINITY;
+    r.ux = !bx || Mx > 0.0;
+    r.uy = !by || My > 0.0;
+    r.uz = !bz || Mz > 0.0;
+    r.cx = (int)floor(r.qx);
+    r.cy = (int)floor(r.qy);
+    r.cz = (int)floor(r.qz);
+    r.t_in = 0.0;
+    r.steps = 0;
+    return true;
+}
+
+__device__ __forceinline__ int advance_axis(bool exit, bool up, int a, int size, double ms,
+                                            double t, double qs) {
+    const int out = up ? a + size : a - 1;
+    int c = (int)floor(fma(ms, t, qs));
+    c = c < a ? a : c;
+    c = c > a + size - 1 ? a + size - 1 : c;
+    return exit ? out : c;
+}
+
+// First half of a step: the leaf that holds the probe.
+template <typename KeyT>
+__device__ __forceinline__ uint32_t ray_locate(const Ray &r, const Tree<KeyT> &t,
+                                               const uint32_t *lut) {
+    return find_leaf(t, morton(lut, r.cx, r.cy, r.cz, KeyT(0)));
+}
+
+// Second half: the chord l of the ray in leaf i, and the probe moved into
+// the next cell; done is set when it has left the box.  The leaf value is
+// not needed here, so its load (issued by the caller between the halves)
+// overlaps with this arithmetic.
+template <typename KeyT>
+__device__ __forceinline__ void ray_advance(Ray &r, const Tree<KeyT> &t, uint32_t i, double &l,
+                                            bool &done) {
+    const int size = 1 << (t.depth - (int)t.levels[i]);
+    const int msk = ~(size - 1);
+    const int ax = r.cx & msk, ay = r.cy & msk, az = r.cz & msk;
+
+    // slab method: far planes of the leaf's box along the ray
+    const double tfx = ((double)(r.ux ? ax + size : ax) - r.qx) * r.ix;
+    const double tfy = ((double)(r.uy ? ay + size : ay) - r.qy) * r.iy;
+    const double tfz = ((double)(r.uz ? az + size : az) - r.qz) * r.iz;
+    double t_out = tfx;
+    if (tfy < t_out) t_out = tfy;
+    if (tfz < t_out) t_out = tfz;
+
+    l = t_out - r.t_in;
+    if (l < 0.0)
+        l = 0.0;
+    else
+        r.t_in = t_out;
+    ++r.steps;
+
+    r.cx = advance_axis(tfx == t_out, r.ux, ax, size, r.mx, t_out, r.qx);
+    r.cy = advance_axis(tfy == t_out, r.uy, ay, size, r.my, t_out, r.qy);
+    r.cz = advance_axis(tfz == t_out, r.uz, az, size, r.mz, t_out, r.qz);
+    const unsigned side = 1u << t.depth;
+    done = ((unsigned)r.cx >= side) | ((unsigned)r.cy >= side) | ((unsigned)r.cz >= side);
+}
+
+// Walks a whole ray; the visitor fetches what it needs of leaf i
+// (Visitor::fetch) as soon as i is known and sees every visited leaf in
+// order (Visitor::step).  Returns the number of leaves, or -1 for an
+// invalid ray or one longer than the 3 * 2^D + 3 steps a valid walk takes.
 template <typename KeyT, typename Visitor>
-__device__ __forceinline__ int walk_ray(const Tree<KeyT> &t, double qx, double qy, double qz,
-                                        double mx, double my, double mz, Visitor &v) {
-    const int D = t.depth;
-    const int side = 1 << D;
-    const double scale = (double)side;  // 2^D, exact
-    const double h = 1.0 / scale;       // 2^-D, exact
-
-    if (!(qx >= 0.0 && qx < 1.0 && qy >= 0.0 && qy < 1.0 && qz >= 0.0 && qz < 1.0)) return -1;
-    if (!(isfinite(mx) && isfinite(my) && isfinite(mz))) return -1;
-    const double ix = 1.0 / mx, iy = 1.0 / my, iz = 1.0 / mz;
-    const bool bx = isfinite(ix), by = isfinite(iy), bz = isfinite(iz);
-    if (!(bx || by || bz)) return -1;
-    const bool px = mx > 0.0, py = my > 0.0, pz = mz > 0.0;
-
-    int cx = (int)floor(qx * scale);
-    int cy = (int)floor(qy * scale);
-    int cz = (int)floor(qz * scale);
-
-    double t_in = 0.0;
-    const int max_steps = 3 * side + 3;
-    int steps = 0;
+__device__ __forceinline__ int walk_ray(const Tree<KeyT> &t, const uint32_t *lut,
+                                        const double *q, const double *m, Visitor &v) {
+    Ray r;
+    if (!ray_init(r, t.depth, q, m)) return -1;
+    const int max_steps = 3 * (1 << t.depth) + 3;
     for (;;) {
-        if (steps >= max_steps) return -1;
-        const KeyT k = morton<KeyT>(cx, cy, cz);
-        const uint32_t i = find_leaf(t, k);
-        const KeyT span = t.keys[i + 1] - t.keys[i];  // 8^(D - level)
-        const int lg = ctz_key(span) / 3;
-        const int size = 1 << lg;
-        const int ax = cx & ~(size - 1);
-        const int ay = cy & ~(size - 1);
-        const int az = cz & ~(size - 1);
-
-        // slab method: far planes of the leaf's box along the ray
-        const double tfx = bx ? ((double)(px ? ax + size : ax) * h - qx) * ix : INFINITY;
-        const double tfy = by ? ((double)(py ? ay + size : ay) * h - qy) * iy : INFINITY;
-        const double tfz = bz ? ((double)(pz ? az + size : az) * h - qz) * iz : INFINITY;
-        double t_out = tfx;
-        if (tfy < t_out) t_out = tfy;
-        if (tfz < t_out) t_out = tfz;
-
-        double l = t_out - t_in;
-        if (l < 0.0)
-            l = 0.0;
-        else
-            t_in = t_out;
-        v.step(i, l);
-        ++steps;
-
-        // advance the probe into the next cell
-        if (bx && tfx == t_out) {
-            cx = px ? ax + size : ax - 1;
-        } else {
-            int c = (int)floor(fma(mx, t_out, qx) * scale);
-            cx = c < ax ? ax : (c > ax + size - 1 ? ax + size - 1 : c);
-        }
-        if (by && tfy == t_out) {
-            cy = py ? ay + size : ay - 1;
-        } else {
-            int c = (int)floor(fma(my, t_out, qy) * scale);
-            cy = c < ay ? ay : (c > ay + size - 1 ? ay + size - 1 : c);
-        }
-        if (bz && tfz == t_out) {
-            cz = pz ? az + size : az - 1;
-        } else {
-            int c = (int)floor(fma(mz, t_out, qz) * scale);
-            cz = c < az ? az : (c > az + size - 1 ? az + size - 1 : c);
-        }
-        if ((unsigned)cx >= (unsigned)side || (unsigned)cy >= (unsigned)side ||
-            (unsigned)cz >= (unsigned)side)
-            break;
+        if (r.steps >= max_steps) return -1;
+        const uint32_t i = ray_locate(r, t, lut);
+        const auto value = v.fetch(i);
+        double l;
+        bool done;
+        ray_advance(r, t, i, l, done);
+        v.step(value, i, l);
+        if (done) break;
     }
-    return steps;
+    return r.steps;
 }
 
 // ---------------------------------------------------------------------
@@ -188,31 +248,26 @@ __device__ __forceinline__ int walk_ray(const Tree<KeyT> &t, double qx, double q
 struct SumF64 {
     const double *__restrict__ rho;
     double N;
-    __device__ __forceinline__ void step(uint32_t i, double l) { N = N + rho[i] * l; }
+    __device__ __forceinline__ double fetch(uint32_t i) const { return rho[i]; }
+    __device__ __forceinline__ void step(double r, uint32_t, double l) { N = N + r * l; }
 };
 
 struct SumF32Kahan {
     const float *__restrict__ rho;
     float S, c;
-    __device__ __forceinline__ void step(uint32_t i, double l) {
-        const float y = rho[i] * (float)l - c;
+    __device__ __forceinline__ float fetch(uint32_t i) const { return rho[i]; }
+    __device__ __forceinline__ void step(float r, uint32_t, double l) {
+        const float y = r * (float)l - c;
         const float t = S + y;
         c = (t - S) - y;
         S = t;
     }
 };
 
-struct ScatterGrad {
-    float *__restrict__ grad;
-    float g;
-    __device__ __forceinline__ void step(uint32_t i, double l) {
-        unsafeAtomicAdd(grad + i, g * (float)l);
-    }
-};
-
 struct HashSteps {
     uint64_t h;
-    __device__ __forceinline__ void step(uint32_t i, double) {
+    __device__ __forceinline__ int fetch(uint32_t) const { return 0; }
+    __device__ __forceinline__ void step(int, uint32_t i, double) {
         h = (h ^ (uint64_t)i) * 0x100000001b3ull;
     }
 };
@@ -221,7 +276,8 @@ struct RecordVisits {
     int32_t *__restrict__ out;
     int64_t cap;
     int64_t n;
-    __device__ __forceinline__ void step(uint32_t i, double) {
+    __device__ __forceinline__ int fetch(uint32_t) const { return 0; }
+    __device__ __forceinline__ void step(int, uint32_t i, double) {
         if (n < cap) out[n] = (int32_t)i;
         ++n;
     }
@@ -240,7 +296,7 @@ __device__ __forceinline__ RayIndex ray_index(const RayBatch &r, int64_t ray) {
 }
 
 // ---------------------------------------------------------------------
-// Kernels
+// Forward kernels
 // ---------------------------------------------------------------------
 
 template <typename KeyT>
@@ -248,14 +304,14 @@ __global__ __launch_bounds__(kBlock) void k_forward_f64(Tree<KeyT> t, RayBatch r
                                                         const double *__restrict__ rho,
                                                         double kappa, double *__restrict__ N,
                                                         double *__restrict__ A, int64_t total) {
+    __shared__ uint32_t lut[1 << kLutBits];
+    init_lut<KeyT>(lut, t.depth);
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t ray = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; ray < total;
          ray += stride) {
         const RayIndex x = ray_index(r, ray);
-        const double *q = r.src + 3 * x.s;
-        const double *m = r.dirs + 3 * x.d;
         SumF64 v{rho, 0.0};
-        const int steps = walk_ray(t, q[0], q[1], q[2], m[0], m[1], m[2], v);
+        const int steps = walk_ray(t, lut, r.src + 3 * x.s, r.dirs + 3 * x.d, v);
         const double n = steps < 0 ? (double)NAN : v.N;
         N[x.off] = n;
         if (A) A[x.off] = exp(-kappa * n);
@@ -267,17 +323,44 @@ __global__ __launch_bounds__(kBlock) void k_forward_f32k(Tree<KeyT> t, RayBatch 
                                                          const float *__restrict__ rho,
                                                          float kappa, float *__restrict__ N,
                                                          float *__restrict__ A, int64_t total) {
+    __shared__ uint32_t lut[1 << kLutBits];
+    init_lut<KeyT>(lut, t.depth);
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t ray = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; ray < total;
          ray += stride) {
         const RayIndex x = ray_index(r, ray);
-        const double *q = r.src + 3 * x.s;
-        const double *m = r.dirs + 3 * x.d;
         SumF32Kahan v{rho, 0.0f, 0.0f};
-        const int steps = walk_ray(t, q[0], q[1], q[2], m[0], m[1], m[2], v);
+        const int steps = walk_ray(t, lut, r.src + 3 * x.s, r.dirs + 3 * x.d, v);
         const float n = steps < 0 ? (float)NAN : v.S;
         N[x.off] = n;
         if (A) A[x.off] = expf(-kappa * n);
+    }
+}
+
+// ---------------------------------------------------------------------
+// Adjoint kernel
+//
+// Every step adds g * l to dL/drho of the leaf.  Neighbouring rays of a
+// wavefront cross the same leaves within a few steps of each other (all of
+// them share a coarse leaf at once), so the additions are first combined
+// in a per-wavefront table in LDS: slot = leaf mod kAggSlots; a lane claims
+// an empty slot with compare-and-swap, adds into a slot holding its leaf
+// with an LDS atomic, and adds straight to global memory on a collision.
+// Every kFlushEvery steps, and when the wavefront finishes, its lanes move
+// the table to global memory with one atomic per occupied slot.  The
+// wavefront steps in lockstep (loop condition uniform over the wavefront)
+// so that all of its lanes take part in every flush.
+// ---------------------------------------------------------------------
+
+__device__ __forceinline__ void flush_table(uint32_t *tag, float *sum, float *__restrict__ grad,
+                                            int lane) {
+    for (int j = lane; j < kAggSlots; j += 64) {
+        const uint32_t k = tag[j];
+        if (k != kEmpty) {
+            unsafeAtomicAdd(grad + k, sum[j]);
+            tag[j] = kEmpty;
+            sum[j] = 0.0f;
+        }
     }
 }
 
@@ -287,33 +370,75 @@ __global__ __launch_bounds__(kBlock) void k_backward(Tree<KeyT> t, RayBatch r, f
                                                      const float *__restrict__ gA,
                                                      const float *__restrict__ A,
                                                      float *__restrict__ grad, int64_t total) {
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t ray = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; ray < total;
-         ray += stride) {
-        const RayIndex x = ray_index(r, ray);
-        float g = gN ? gN[x.off] : 0.0f;
-        if (gA) g = g - kappa * A[x.off] * gA[x.off];
-        if (g == 0.0f) continue;  // the ray adds nothing
-        const double *q = r.src + 3 * x.s;
-        const double *m = r.dirs + 3 * x.d;
-        ScatterGrad v{grad, g};
-        walk_ray(t, q[0], q[1], q[2], m[0], m[1], m[2], v);
+    __shared__ uint32_t lut[1 << kLutBits];
+    __shared__ uint32_t s_tag[kWaves][kAggSlots];
+    __shared__ float s_sum[kWaves][kAggSlots];
+    const int wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    uint32_t *tag = s_tag[wave];
+    float *sum = s_sum[wave];
+    for (int j = lane; j < kAggSlots; j += 64) {
+        tag[j] = kEmpty;
+        sum[j] = 0.0f;
     }
+    init_lut<KeyT>(lut, t.depth);  // ends with a block barrier
+    const int max_steps = 3 * (1 << t.depth) + 3;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    int since_flush = 0;
+    // base is uniform over the wavefront: all its lanes run every iteration
+    for (int64_t base = (int64_t)blockIdx.x * blockDim.x + (wave << 6); base < total;
+         base += stride) {
+        const int64_t ray = base + lane;
+        Ray st;
+        float g = 0.0f;
+        bool active = false;
+        if (ray < total) {
+            const RayIndex x = ray_index(r, ray);
+            g = gN ? gN[x.off] : 0.0f;
+            if (gA) g = g - kappa * A[x.off] * gA[x.off];
+            if (g != 0.0f) active = ray_init(st, t.depth, r.src + 3 * x.s, r.dirs + 3 * x.d);
+        }
+        while (__any(active)) {
+            if (active) {
+                double l;
+                bool done;
+                const uint32_t leaf = ray_locate(st, t, lut);
+                ray_advance(st, t, leaf, l, done);
+                const float v = g * (float)l;
+                const int slot = (int)(leaf & (kAggSlots - 1));
+                const uint32_t old = atomicCAS(tag + slot, kEmpty, leaf);
+                if (old == kEmpty || old == leaf)
+                    atomicAdd(sum + slot, v);
+                else
+                    unsafeAtomicAdd(grad + leaf, v);
+                if (done || st.steps >= max_steps) active = false;
+            }
+            if (++since_flush == kFlushEvery) {
+                flush_table(tag, sum, grad, lane);
+                since_flush = 0;
+            }
+        }
+    }
+    flush_table(tag, sum, grad, lane);
 }
+
+// ---------------------------------------------------------------------
+// Trace kernels
+// ---------------------------------------------------------------------
 
 template <typename KeyT>
 __global__ __launch_bounds__(kBlock) void k_trace(Tree<KeyT> t, RayBatch r,
                                                   int32_t *__restrict__ steps_out,
                                                   uint64_t *__restrict__ hash_out,
                                                   int64_t total) {
+    __shared__ uint32_t lut[1 << kLutBits];
+    init_lut<KeyT>(lut, t.depth);
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t ray = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; ray < total;
          ray += stride) {
         const RayIndex x = ray_index(r, ray);
-        const double *q = r.src + 3 * x.s;
-        const double *m = r.dirs + 3 * x.d;
         HashSteps v{0xcbf29ce484222325ull};
-        const int steps = walk_ray(t, q[0], q[1], q[2], m[0], m[1], m[2], v);
+        const int steps = walk_ray(t, lut, r.src + 3 * x.s, r.dirs + 3 * x.d, v);
         if (steps_out) steps_out[x.off] = steps;
         if (hash_out) hash_out[x.off] = v.h;
     }
@@ -325,6 +450,8 @@ __global__ __launch_bounds__(kBlock) void k_trace_sample(Tree<KeyT> t, RayBatch 
                                                          int64_t n_sample,
                                                          int32_t *__restrict__ visited,
                                                          int64_t cap, int64_t total) {
+    __shared__ uint32_t lut[1 << kLutBits];
+    init_lut<KeyT>(lut, t.depth);
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= n_sample) return;
     int32_t *out = visited + j * cap;
@@ -332,10 +459,8 @@ __global__ __launch_bounds__(kBlock) void k_trace_sample(Tree<KeyT> t, RayBatch 
     int64_t n = 0;
     if (ray >= 0 && ray < total) {
         const RayIndex x = ray_index(r, ray);
-        const double *q = r.src + 3 * x.s;
-        const double *m = r.dirs + 3 * x.d;
         RecordVisits v{out, cap, 0};
-        walk_ray(t, q[0], q[1], q[2], m[0], m[1], m[2], v);
+        walk_ray(t, lut, r.src + 3 * x.s, r.dirs + 3 * x.d, v);
         n = v.n;
     }
     for (int64_t e = n; e < cap; ++e) out[e] = -1;
@@ -345,6 +470,7 @@ template <typename KeyT>
 Tree<KeyT> tree_of(const TreeView &v) {
     Tree<KeyT> t;
     t.keys = static_cast<const KeyT *>(v.keys);
+    t.levels = v.levels;
     t.top = v.top;
     t.depth = v.depth;
     t.top_shift = 3 * (v.depth - v.top_level);
@@ -359,7 +485,13 @@ unsigned grid_for(int64_t total) {
 
 }  // namespace
 
-int top_table_level(int depth) { return depth < kTopLevelMax ? depth : kTopLevelMax; }
+// The top table has at most two entries per leaf (8 bytes per leaf), at the
+// deepest level that allows, capped at the tree depth and at kTopLevelMax.
+int top_table_level(int depth, int64_t n_leaves) {
+    int lt = 0;
+    while (lt < depth && lt < kTopLevelMax && ((int64_t)1 << (3 * (lt + 1))) <= 2 * n_leaves) ++lt;
+    return lt;
+}
 
 hipError_t launch_forward(const TreeView &tree, const RayBatch &rays, const void *rho,
                           int precision, double kappa, void *N, void *A, hipStream_t stream) {

@@ -148,14 +148,15 @@ int rt_columns(const rt_octree *tree, const void *d_rho, int precision, const do
  *   d_gN     device f32, dL/dN at the rt_columns offsets, or NULL (= 0);
  *   d_gA     device f32, dL/dA, or NULL (= 0);
  *   d_A      device f32, the A of the forward call; required iff d_gA;
- *   d_grad_rho device f32 [n_leaves], accumulated with atomic adds (the
+ *   d_grad_rho device f64 [n_leaves], accumulated with atomic adds (the
  *            caller zeroes it); the summation order is not deterministic.
- * The traversal is the FP64 one of rt_columns; g * r is formed in FP32.
- * Errors: RT_ERR_ARG, RT_ERR_DEVICE. */
+ * The traversal is the FP64 one of rt_columns; g * r is formed in FP32,
+ * summed in FP32 over a few steps of neighbouring rays, then added to the
+ * FP64 accumulator.  Errors: RT_ERR_ARG, RT_ERR_DEVICE. */
 int rt_columns_backward(const rt_octree *tree, const double *d_src, int64_t n_src,
                         const double *d_dirs, int64_t n_dirs, double kappa, const float *d_gN,
                         const float *d_gA, const float *d_A, int64_t stride_src,
-                        int64_t stride_dir, float *d_grad_rho, void *stream);
+                        int64_t stride_dir, double *d_grad_rho, void *stream);
 
 /* Traversal record of every ray, for verification: the number of leaves
  * visited and a 64-bit FNV-1a-style hash of the visited leaf indices

@@ -289,7 +289,7 @@ int rt_columns(const rt_octree *tree, const void *d_rho, int precision, const do
 int rt_columns_backward(const rt_octree *tree, const double *d_src, int64_t n_src,
                         const double *d_dirs, int64_t n_dirs, double kappa, const float *d_gN,
                         const float *d_gA, const float *d_A, int64_t stride_src,
-                        int64_t stride_dir, float *d_grad_rho, void *stream) {
+                        int64_t stride_dir, double *d_grad_rho, void *stream) {
     rt::RayBatch rays;
     int st = check_rays(tree, d_src, n_src, d_dirs, n_dirs, stride_src, stride_dir, &rays);
     if (st != RT_OK) return st;

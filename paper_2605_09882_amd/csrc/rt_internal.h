@@ -40,7 +40,7 @@ hipError_t launch_forward(const TreeView &tree, const RayBatch &rays, const void
                           int precision, double kappa, void *N, void *A, hipStream_t stream);
 
 hipError_t launch_backward(const TreeView &tree, const RayBatch &rays, double kappa,
-                           const float *gN, const float *gA, const float *A, float *grad,
+                           const float *gN, const float *gA, const float *A, double *grad,
                            hipStream_t stream);
 
 hipError_t launch_trace(const TreeView &tree, const RayBatch &rays, int32_t *steps,

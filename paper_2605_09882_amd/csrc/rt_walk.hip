@@ -44,10 +44,12 @@ constexpr int kWaves = kBlock / 64;
 constexpr int kTopLevelMax = 9;     // at most 8^9 + 1 table entries (512 MB)
 constexpr int kLutBits = 10;        // Morton spread table covers depths <= 10
 
-// Adjoint scatter aggregation: per wavefront, a direct-mapped table in LDS
-// of (leaf, partial dL/drho) pairs, flushed to global memory every
-// kFlushEvery steps of the wavefront and at its end.
+// Adjoint scatter aggregation: per wavefront, a kAggWays-way set-associative
+// table in LDS of (leaf, partial dL/drho) pairs, moved to global memory
+// every kFlushEvery steps of the wavefront and when it ends.
 constexpr int kAggSlots = 512;
+constexpr int kAggWays = 4;
+constexpr int kAggSets = kAggSlots / kAggWays;
 constexpr int kFlushEvery = 16;
 constexpr uint32_t kEmpty = 0xffffffffu;
 
@@ -88,6 +90,7 @@ struct Tree {
     const KeyT *__restrict__ keys;      // n + 1 keys (sentinel 8^D last)
     const uint8_t *__restrict__ levels;  // n leaf levels
     const uint32_t *__restrict__ top;   // 8^top_level + 1 leaf indices
+    KeyT cell_mask;  // 8^(depth - top_level) - 1: keys per table cell, minus one
     int depth;
     int top_shift;  // 3 * (depth - top_level)
 };
@@ -107,12 +110,17 @@ __device__ __forceinline__ void init_lut(uint32_t *lut, int depth) {
 // that leaf covers all of cell c; otherwise the leaves of cell c are exactly
 // top[c] .. top[c+1]-1 (a leaf starting before the next cell's first key
 // and reaching into it would be coarser than the cell and cover all of it).
+// A cell with as many leaves as finest cells is refined to the maximum
+// depth everywhere, and its leaves follow the keys one to one.  Only the
+// remaining, partly refined cells need a binary search over the keys.
 template <typename KeyT>
 __device__ __forceinline__ uint32_t find_leaf(const Tree<KeyT> &t, KeyT k) {
     const uint32_t c = (uint32_t)(k >> t.top_shift);
     uint32_t lo = t.top[c];
     const uint32_t nx = t.top[c + 1];
-    uint32_t hi = nx == lo ? lo + 1u : nx;
+    if (nx == lo) return lo;
+    if ((KeyT)(nx - lo) == t.cell_mask + 1) return lo + (uint32_t)(k & t.cell_mask);
+    uint32_t hi = nx;
     while (hi - lo > 1u) {
         const uint32_t mid = (lo + hi) >> 1;
         if (t.keys[mid] <= k)
@@ -340,24 +348,30 @@ __global__ __launch_bounds__(kBlock) void k_forward_f32k(Tree<KeyT> t, RayBatch 
 // ---------------------------------------------------------------------
 // Adjoint kernel
 //
-// Every step adds g * l to dL/drho of the leaf.  Neighbouring rays of a
+// Every step adds g * l (formed in FP32) to dL/drho of the leaf, which is
+// accumulated in FP64: a coarse leaf collects the contributions of millions
+// of rays, and in an FP32 running sum the late, small ones would be rounded
+// away.  Neighbouring rays of a
 // wavefront cross the same leaves within a few steps of each other (all of
 // them share a coarse leaf at once), so the additions are first combined
-// in a per-wavefront table in LDS: slot = leaf mod kAggSlots; a lane claims
-// an empty slot with compare-and-swap, adds into a slot holding its leaf
-// with an LDS atomic, and adds straight to global memory on a collision.
-// Every kFlushEvery steps, and when the wavefront finishes, its lanes move
-// the table to global memory with one atomic per occupied slot.  The
-// wavefront steps in lockstep (loop condition uniform over the wavefront)
-// so that all of its lanes take part in every flush.
+// in a per-wavefront table in LDS.  The leaf selects a set of kAggWays
+// slots (set = leaf mod kAggSets); a lane reads the set's tags at once and
+// adds into the slot holding its leaf with an LDS atomic, or claims the
+// first empty slot with compare-and-swap (a lane of the same instruction
+// that raced it to that slot with the same leaf just adds), or, when the set
+// is full, adds straight to global memory.  Every kFlushEvery steps, and
+// when the wavefront finishes, its lanes move the table to global memory
+// with one atomic per occupied slot.  The wavefront steps in lockstep (loop
+// condition uniform over the wavefront) so that all of its lanes take part
+// in every flush.
 // ---------------------------------------------------------------------
 
-__device__ __forceinline__ void flush_table(uint32_t *tag, float *sum, float *__restrict__ grad,
+__device__ __forceinline__ void flush_table(uint32_t *tag, float *sum, double *__restrict__ grad,
                                             int lane) {
     for (int j = lane; j < kAggSlots; j += 64) {
         const uint32_t k = tag[j];
         if (k != kEmpty) {
-            unsafeAtomicAdd(grad + k, sum[j]);
+            unsafeAtomicAdd(grad + k, (double)sum[j]);
             tag[j] = kEmpty;
             sum[j] = 0.0f;
         }
@@ -369,7 +383,7 @@ __global__ __launch_bounds__(kBlock) void k_backward(Tree<KeyT> t, RayBatch r, f
                                                      const float *__restrict__ gN,
                                                      const float *__restrict__ gA,
                                                      const float *__restrict__ A,
-                                                     float *__restrict__ grad, int64_t total) {
+                                                     double *__restrict__ grad, int64_t total) {
     __shared__ uint32_t lut[1 << kLutBits];
     __shared__ uint32_t s_tag[kWaves][kAggSlots];
     __shared__ float s_sum[kWaves][kAggSlots];
@@ -405,12 +419,23 @@ __global__ __launch_bounds__(kBlock) void k_backward(Tree<KeyT> t, RayBatch r, f
                 const uint32_t leaf = ray_locate(st, t, lut);
                 ray_advance(st, t, leaf, l, done);
                 const float v = g * (float)l;
-                const int slot = (int)(leaf & (kAggSlots - 1));
-                const uint32_t old = atomicCAS(tag + slot, kEmpty, leaf);
-                if (old == kEmpty || old == leaf)
+                const int set = (int)(leaf & (kAggSets - 1)) * kAggWays;
+                int slot = -1;
+                int empty = -1;
+#pragma unroll
+                for (int way = 0; way < kAggWays; ++way) {
+                    const uint32_t tg = tag[set + way];
+                    if (tg == leaf) slot = set + way;
+                    if (tg == kEmpty && empty < 0) empty = set + way;
+                }
+                if (slot < 0 && empty >= 0) {
+                    const uint32_t old = atomicCAS(tag + empty, kEmpty, leaf);
+                    if (old == kEmpty || old == leaf) slot = empty;
+                }
+                if (slot >= 0)
                     atomicAdd(sum + slot, v);
                 else
-                    unsafeAtomicAdd(grad + leaf, v);
+                    unsafeAtomicAdd(grad + leaf, (double)v);
                 if (done || st.steps >= max_steps) active = false;
             }
             if (++since_flush == kFlushEvery) {
@@ -474,6 +499,9 @@ Tree<KeyT> tree_of(const TreeView &v) {
     t.top = v.top;
     t.depth = v.depth;
     t.top_shift = 3 * (v.depth - v.top_level);
+    // keys per table cell; beyond 2^32 no cell can hold that many leaves
+    const int bits = 3 * (v.depth - v.top_level);
+    t.cell_mask = bits >= 8 * (int)sizeof(KeyT) ? (KeyT)~KeyT(0) : (KeyT)((KeyT(1) << bits) - 1);
     return t;
 }
 
@@ -520,7 +548,7 @@ hipError_t launch_forward(const TreeView &tree, const RayBatch &rays, const void
 }
 
 hipError_t launch_backward(const TreeView &tree, const RayBatch &rays, double kappa,
-                           const float *gN, const float *gA, const float *A, float *grad,
+                           const float *gN, const float *gA, const float *A, double *grad,
                            hipStream_t stream) {
     const int64_t total = rays.n_src * rays.n_dirs;
     const unsigned grid = grid_for(total);

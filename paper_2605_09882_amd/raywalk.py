@@ -126,7 +126,7 @@ def _dir_major_f32(x, S, Dn, dev):
 
 
 def columns_backward(tree, src, dirs, kappa, gN=None, gA=None, A=None, grad=None):
-    """Adds dL/drho (float32, [n_leaves]) into grad (created zeroed if None)."""
+    """Adds dL/drho (float64, [n_leaves]) into grad (created zeroed if None)."""
     dev = tree.device
     src = _as_dev(src, torch.float64, dev, 3)
     dirs = _as_dev(dirs, torch.float64, dev, 3)
@@ -135,9 +135,9 @@ def columns_backward(tree, src, dirs, kappa, gN=None, gA=None, A=None, grad=None
     gA = _dir_major_f32(gA, S, Dn, dev)
     A = _dir_major_f32(A, S, Dn, dev) if gA is not None else None
     if grad is None:
-        grad = torch.zeros(tree.n, dtype=torch.float32, device=dev)
-    elif grad.dtype != torch.float32 or grad.numel() != tree.n or not grad.is_contiguous():
-        raise ValueError("grad must be a contiguous float32 tensor with one value per leaf")
+        grad = torch.zeros(tree.n, dtype=torch.float64, device=dev)
+    elif grad.dtype != torch.float64 or grad.numel() != tree.n or not grad.is_contiguous():
+        raise ValueError("grad must be a contiguous float64 tensor with one value per leaf")
     _abi.rt_columns_backward(tree.handle, src.data_ptr(), S, dirs.data_ptr(), Dn, kappa,
                              _ptr(gN), _ptr(gA), _ptr(A), 1, S, grad.data_ptr(), _stream(dev))
     return grad

@@ -52,6 +52,14 @@ constexpr int kAggWays = 4;
 constexpr int kAggSets = kAggSlots / kAggWays;
 constexpr int kFlushEvery = 16;
 constexpr uint32_t kEmpty = 0xffffffffu;
+// Before the table, lanes that share a leaf in the same step are summed
+// across the wavefront: the groups of the first kMaxPeel pending lanes are
+// examined, and those of at least kPeelMin lanes are summed.
+constexpr int kPeelMin = 4;
+constexpr int kMaxPeel = 2;
+// Owner election cells per wavefront (slot mod kOwnerSlots; an alias only
+// turns an owner into an atomic adder).
+constexpr int kOwnerSlots = 128;
 
 // ---------------------------------------------------------------------
 // Morton keys: spread the bits of each coordinate three apart.
@@ -208,9 +216,10 @@ __device__ __forceinline__ void ray_advance(Ray &r, const Tree<KeyT> &t, uint32_
     const double tfx = ((double)(r.ux ? ax + size : ax) - r.qx) * r.ix;
     const double tfy = ((double)(r.uy ? ay + size : ay) - r.qy) * r.iy;
     const double tfz = ((double)(r.uz ? az + size : az) - r.qz) * r.iz;
-    double t_out = tfx;
-    if (tfy < t_out) t_out = tfy;
-    if (tfz < t_out) t_out = tfz;
+    // min in the order x, y, z; the far times are never +0 (a zero far time
+    // is (0) * (negative 1/m) = -0) nor NaN, so fmin returns the same bits
+    // as the compare chain
+    const double t_out = fmin(fmin(tfx, tfy), tfz);
 
     l = t_out - r.t_in;
     if (l < 0.0)
@@ -219,9 +228,18 @@ __device__ __forceinline__ void ray_advance(Ray &r, const Tree<KeyT> &t, uint32_
         r.t_in = t_out;
     ++r.steps;
 
-    r.cx = advance_axis(tfx == t_out, r.ux, ax, size, r.mx, t_out, r.qx);
-    r.cy = advance_axis(tfy == t_out, r.uy, ay, size, r.my, t_out, r.qy);
-    r.cz = advance_axis(tfz == t_out, r.uz, az, size, r.mz, t_out, r.qz);
+    const bool ex = tfx == t_out, ey = tfy == t_out, ez = tfz == t_out;
+    if (size == 1) {
+        // finest leaf: the clamp to the leaf leaves every non-exit axis on
+        // the probe's own cell, so only the exit axes move (a plain DDA step)
+        r.cx = ex ? (r.ux ? ax + 1 : ax - 1) : ax;
+        r.cy = ey ? (r.uy ? ay + 1 : ay - 1) : ay;
+        r.cz = ez ? (r.uz ? az + 1 : az - 1) : az;
+    } else {
+        r.cx = advance_axis(ex, r.ux, ax, size, r.mx, t_out, r.qx);
+        r.cy = advance_axis(ey, r.uy, ay, size, r.my, t_out, r.qy);
+        r.cz = advance_axis(ez, r.uz, az, size, r.mz, t_out, r.qz);
+    }
     const unsigned side = 1u << t.depth;
     done = ((unsigned)r.cx >= side) | ((unsigned)r.cy >= side) | ((unsigned)r.cz >= side);
 }
@@ -354,7 +372,8 @@ __global__ __launch_bounds__(kBlock) void k_forward_f32k(Tree<KeyT> t, RayBatch 
 // away.  Neighbouring rays of a
 // wavefront cross the same leaves within a few steps of each other (all of
 // them share a coarse leaf at once), so the additions are first combined
-// in a per-wavefront table in LDS.  The leaf selects a set of kAggWays
+// in a per-wavefront table in LDS (after lanes of the same step that share
+// a leaf have been summed across the wavefront).  The leaf selects a set of kAggWays
 // slots (set = leaf mod kAggSets); a lane reads the set's tags at once and
 // adds into the slot holding its leaf with an LDS atomic, or claims the
 // first empty slot with compare-and-swap (a lane of the same instruction
@@ -365,6 +384,63 @@ __global__ __launch_bounds__(kBlock) void k_forward_f32k(Tree<KeyT> t, RayBatch 
 // condition uniform over the wavefront) so that all of its lanes take part
 // in every flush.
 // ---------------------------------------------------------------------
+
+// Sum of v over the 64 lanes of the wavefront (all lanes must be active),
+// with DPP lane shifts only: an inclusive scan inside each row of 16 lanes
+// (shifts by 1, 2, 4, 8 lanes), then the row totals carried across rows
+// (row broadcasts of lanes 15 and 31); lane 63 ends with the total.
+template <int kCtrl, int kRowMask, bool kBoundZero>
+__device__ __forceinline__ float dpp(float src) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, src),
+                                                                 kCtrl, kRowMask, 0xf, kBoundZero));
+}
+
+__device__ __forceinline__ float wave_total(float v) {
+    v += dpp<0x111, 0xf, true>(v);   // row_shr:1
+    v += dpp<0x112, 0xf, true>(v);   // row_shr:2
+    v += dpp<0x114, 0xf, true>(v);   // row_shr:4
+    v += dpp<0x118, 0xf, true>(v);   // row_shr:8
+    v += dpp<0x142, 0xa, false>(v);  // row_bcast:15 into rows 1 and 3
+    v += dpp<0x143, 0xc, false>(v);  // row_bcast:31 into rows 2 and 3
+    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 63));
+}
+
+// Adds v to the table entry of leaf (or to global memory when its set is
+// full).  Called by every lane of the wavefront with a pending value, in
+// the same instruction.  LDS atomic adds are slow when many lanes issue
+// them, so the lanes first elect one owner per slot (each writes its lane
+// number into owner[slot], the value that sticks names the owner): the
+// owner adds with a plain load and store, and only the other lanes of that
+// slot -- lanes of the same step on the same leaf -- add atomically, after
+// the owner's store.
+__device__ __forceinline__ void table_add(uint32_t *tag, float *sum, uint32_t *owner,
+                                          double *__restrict__ grad, uint32_t leaf, float v,
+                                          bool pending, int lane) {
+    int slot = -1;
+    if (pending) {
+        const int set = (int)(leaf & (kAggSets - 1)) * kAggWays;
+        int empty = -1;
+#pragma unroll
+        for (int way = 0; way < kAggWays; ++way) {
+            const uint32_t tg = tag[set + way];
+            if (tg == leaf) slot = set + way;
+            if (tg == kEmpty && empty < 0) empty = set + way;
+        }
+        if (slot < 0 && empty >= 0) {
+            const uint32_t old = atomicCAS(tag + empty, kEmpty, leaf);
+            if (old == kEmpty || old == leaf) slot = empty;
+        }
+        if (slot < 0) unsafeAtomicAdd(grad + leaf, (double)v);
+    }
+    uint32_t *cell = owner + (slot & (kOwnerSlots - 1));
+    if (slot >= 0)
+        __hip_atomic_store(cell, (uint32_t)lane, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    const bool own = slot >= 0 && __hip_atomic_load(cell, __ATOMIC_RELAXED,
+                                                     __HIP_MEMORY_SCOPE_WORKGROUP) == (uint32_t)lane;
+    if (own) sum[slot] = sum[slot] + v;
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);  // the owners' stores come first
+    if (slot >= 0 && !own) atomicAdd(sum + slot, v);
+}
 
 __device__ __forceinline__ void flush_table(uint32_t *tag, float *sum, double *__restrict__ grad,
                                             int lane) {
@@ -387,10 +463,12 @@ __global__ __launch_bounds__(kBlock) void k_backward(Tree<KeyT> t, RayBatch r, f
     __shared__ uint32_t lut[1 << kLutBits];
     __shared__ uint32_t s_tag[kWaves][kAggSlots];
     __shared__ float s_sum[kWaves][kAggSlots];
+    __shared__ uint32_t s_owner[kWaves][kOwnerSlots];
     const int wave = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
     uint32_t *tag = s_tag[wave];
     float *sum = s_sum[wave];
+    uint32_t *owner = s_owner[wave];
     for (int j = lane; j < kAggSlots; j += 64) {
         tag[j] = kEmpty;
         sum[j] = 0.0f;
@@ -413,31 +491,37 @@ __global__ __launch_bounds__(kBlock) void k_backward(Tree<KeyT> t, RayBatch r, f
             if (g != 0.0f) active = ray_init(st, t.depth, r.src + 3 * x.s, r.dirs + 3 * x.d);
         }
         while (__any(active)) {
+            uint32_t leaf = kEmpty;
+            float v = 0.0f;
             if (active) {
                 double l;
                 bool done;
-                const uint32_t leaf = ray_locate(st, t, lut);
+                leaf = ray_locate(st, t, lut);
                 ray_advance(st, t, leaf, l, done);
-                const float v = g * (float)l;
-                const int set = (int)(leaf & (kAggSets - 1)) * kAggWays;
-                int slot = -1;
-                int empty = -1;
-#pragma unroll
-                for (int way = 0; way < kAggWays; ++way) {
-                    const uint32_t tg = tag[set + way];
-                    if (tg == leaf) slot = set + way;
-                    if (tg == kEmpty && empty < 0) empty = set + way;
-                }
-                if (slot < 0 && empty >= 0) {
-                    const uint32_t old = atomicCAS(tag + empty, kEmpty, leaf);
-                    if (old == kEmpty || old == leaf) slot = empty;
-                }
-                if (slot >= 0)
-                    atomicAdd(sum + slot, v);
-                else
-                    unsafeAtomicAdd(grad + leaf, (double)v);
+                v = g * (float)l;
                 if (done || st.steps >= max_steps) active = false;
             }
+            // all 64 lanes are active here: sum the groups of lanes that
+            // share a leaf (coarse leaves hold many rays at once)
+            bool pending = leaf != kEmpty;
+            bool cand = pending;  // not yet examined for a shared leaf
+            for (int peel = 0; peel < kMaxPeel; ++peel) {
+                const uint64_t cm = __ballot(cand);
+                if (cm == 0) break;
+                const int leader = __ffsll((unsigned long long)cm) - 1;
+                const uint32_t L = (uint32_t)__builtin_amdgcn_readlane((int)leaf, leader);
+                const bool mine = cand && leaf == L;
+                if (__popcll(__ballot(mine)) >= kPeelMin) {
+                    const float total = wave_total(mine ? v : 0.0f);
+                    if (mine) {
+                        // the group's total travels in the leader's lane
+                        v = lane == leader ? total : 0.0f;
+                        pending = lane == leader;
+                    }
+                }
+                if (mine) cand = false;
+            }
+            table_add(tag, sum, owner, grad, leaf, v, pending, lane);
             if (++since_flush == kFlushEvery) {
                 flush_table(tag, sum, grad, lane);
                 since_flush = 0;

@@ -28,7 +28,10 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+VALU_PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9  # CUs x SIMDs x lanes x clock
 CPU_SAMPLE_STRIDE = 4096
+BYTES_PER_STEP = {"k_forward_f32k": 13, "k_forward_f64": 17, "k_backward": 25}
+BYTES_PER_RAY = {"k_forward_f32k": 32, "k_forward_f64": 40, "k_backward": 32}
 
 
 def log(msg):
@@ -56,9 +59,11 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def stored_traffic(kernel, workload, src_hash):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if
-    it was taken on the current kernel sources."""
+def stored_counters(kernel, workload, src_hash):
+    """The committed rocprofv3 counter summary of this kernel and workload
+    (HBM bytes per launch from FETCH_SIZE + WRITE_SIZE, scaled against a
+    copy of known size; VALU issue rate), if it was taken on the current
+    kernel sources; else None."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     try:
         with open(path) as fh:
@@ -68,7 +73,7 @@ def stored_traffic(kernel, workload, src_hash):
     e = rec.get(workload, {}).get(kernel)
     if not e or e.get("source_hash") != src_hash:
         return None
-    return e.get("hbm_bytes_per_launch")
+    return e
 
 
 def stream_copy_gbs(torch, dev, gb):
@@ -210,25 +215,37 @@ def main():
         b.record()
         torch.cuda.synchronize()
         ms64 = a.elapsed_time(b) / args.steps
+        b64 = total_steps * BYTES_PER_STEP["k_forward_f64"] + rays * BYTES_PER_RAY["k_forward_f64"]
         fp64 = {"ms": round(ms64, 3), "steps_per_s": total_steps / (ms64 / 1e3),
-                "bytes_per_step": 12}
+                "algorithmic_gbs": round(b64 / (ms64 / 1e3) / 1e9, 1)}
         del N64
         log(f"FP64 walk {ms64:.1f} ms")
 
-    # roofline of the dominant kernel (algorithmic bytes per launch / duration)
-    fwd_bytes = total_steps * (1 + 4) + rays * (24 + 4 + 4)
-    bwd_bytes = total_steps * (1 + 16) + rays * (24 + 4 + 4)
+    # roofline of the dominant kernel: algorithmic bytes per launch over its
+    # measured duration.  Per ray-leaf step the method reads one leaf record
+    # (Morton key 8 B, level 1 B, value 4 B FP32 / 8 B FP64); the adjoint
+    # reads key and level and adds into an FP64 gradient (8 B read + 8 B
+    # written).  Per ray: the source (24 B) plus N and A (FP32), or the
+    # upstream gradient and A read by the adjoint.
+    fwd_bytes = total_steps * BYTES_PER_STEP["k_forward_f32k"] + rays * BYTES_PER_RAY["k_forward_f32k"]
+    bwd_bytes = total_steps * BYTES_PER_STEP["k_backward"] + rays * BYTES_PER_RAY["k_backward"]
     if bwd_ms >= fwd_ms:
         kname, kms, kbytes = "k_backward", bwd_ms, bwd_bytes
     else:
         kname, kms, kbytes = "k_forward_f32k", fwd_ms, fwd_bytes
     achieved = kbytes / (kms / 1e3) / 1e9
     src_hash = kernel_source_hash()
-    traffic = stored_traffic(kname, w.name, src_hash)
+    prof = stored_counters(kname, w.name, src_hash)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": prof["hbm_bytes_per_launch"] if prof else None,
                 "kernel": kname, "kernel_ms": round(kms, 3), "algorithmic_bytes": kbytes,
-                "achievable_gbs": round(copy["gbs"], 1) if copy else None}
+                "bytes_per_step": BYTES_PER_STEP[kname], "bytes_per_ray": BYTES_PER_RAY[kname],
+                "achievable_gbs": round(copy["gbs"], 1) if copy else None,
+                "frac_of_achievable": round(achieved / copy["gbs"], 4) if copy else None,
+                "l2_hit_rate": prof["l2_hit_rate"] if prof else None,
+                "valu_frac": (round(prof["valu_lane_ops_per_s"] / VALU_PEAK_LANE_OPS, 3)
+                              if prof else None)}
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -55,7 +55,8 @@ Layout workspace_layout(int64_t n, int depth) {
     return l;
 }
 
-constexpr int64_t kMaxLeaves = ((int64_t)1 << 31) - 2;  // leaf indices are 32-bit
+// Leaf indices travel in the low 30 bits of a top-table entry.
+constexpr int64_t kMaxLeaves = ((int64_t)1 << 30) - 2;
 
 bool valid_precision(int p) { return p == RT_FP64 || p == RT_FP32_KAHAN; }
 
@@ -186,7 +187,7 @@ int rt_build_octree(const uint64_t *keys, const uint8_t *levels, int64_t n_leave
     if (!keys || !levels) return fail(RT_ERR_ARG, "null keys or levels");
     if (max_depth < 1 || max_depth > 21) return fail(RT_ERR_ARG, "max_depth %d not in 1..21", max_depth);
     if (n_leaves < 1 || n_leaves > kMaxLeaves)
-        return fail(RT_ERR_ARG, "n_leaves %lld not in 1..2^31-2", (long long)n_leaves);
+        return fail(RT_ERR_ARG, "n_leaves %lld not in 1..2^30-2", (long long)n_leaves);
     const int D = max_depth;
     for (int64_t i = 1; i < n_leaves; ++i)
         if (keys[i] <= keys[i - 1])
@@ -237,6 +238,19 @@ int rt_build_octree(const uint64_t *keys, const uint8_t *levels, int64_t n_leave
         top[c] = (uint32_t)i;
     }
     top[ncell] = (uint32_t)n_leaves;
+    // flags: the cell is refined to depth D everywhere (its leaves follow its
+    // keys one to one), or a single leaf covers it.  As many leaves as
+    // finest cells means depth D throughout, except for a one-cell table
+    // cell, which also meets that count when it is the last finest cell of
+    // a coarser leaf: hence the level test.
+    const int64_t per_cell = shift < 31 ? (int64_t)1 << shift : INT64_MAX;
+    for (int64_t c = 0; c < ncell; ++c) {
+        const int64_t lo = top[c], nx = top[c + 1] & rt::kTopIndex;
+        if (nx - lo == per_cell && levels[lo] == D)
+            top[c] |= rt::kTopFull;
+        else if (levels[lo] <= lt)
+            top[c] |= rt::kTopOne;
+    }
 
     int device = 0;
     hipError_t e = hipGetDevice(&device);

@@ -7,6 +7,15 @@
 
 namespace rt {
 
+// Top-table entry: the leaf index in the low 30 bits, plus
+//   kTopFull: the cell is refined to the maximum depth everywhere, so leaf
+//             index = entry + (key mod keys per cell) and level = D;
+//   kTopOne:  a single leaf (the entry's) covers the whole cell.
+// Without either flag the cell's leaves are entry .. next entry - 1.
+constexpr uint32_t kTopFull = 0x80000000u;
+constexpr uint32_t kTopOne = 0x40000000u;
+constexpr uint32_t kTopIndex = 0x3fffffffu;
+
 // Device view of a built octree.  keys holds n+1 entries: the n leaf keys
 // and a sentinel 8^D, narrowed to 32 bits when D <= 10; levels the n leaf
 // levels.  top[c] for the

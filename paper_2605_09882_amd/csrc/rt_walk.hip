@@ -15,7 +15,7 @@
 //         far-plane times tf_a = (plane_a h - Q_a) / m_a for bounding axes
 //         (1/m_a finite), +inf for the others;
 //         t_out = min(tf_x, tf_y, tf_z) in that order;
-//         l = t_out - t_in (clamped at 0), accumulate rho_i l;
+//         l = t_out - t_in (clamped at 0, t_in kept), accumulate rho_i l;
 //         axes with tf_a == t_out step to the neighbour cell, the others
 //         take floor(fma(m_a, t_out, Q_a) 2^D) clamped to the leaf;
 //         stop when p leaves [0, 2^D)^3.
@@ -56,7 +56,7 @@ constexpr uint32_t kEmpty = 0xffffffffu;
 // across the wavefront: the groups of the first kMaxPeel pending lanes are
 // examined, and those of at least kPeelMin lanes are summed.
 constexpr int kPeelMin = 4;
-constexpr int kMaxPeel = 2;
+constexpr int kMaxPeel = 1;
 // Owner election cells per wavefront (slot mod kOwnerSlots; an alias only
 // turns an owner into an atomic adder).
 constexpr int kOwnerSlots = 128;
@@ -113,29 +113,33 @@ __device__ __forceinline__ void init_lut(uint32_t *lut, int depth) {
     __syncthreads();
 }
 
-// Largest leaf index i with keys[i] <= k.  top[c] is the leaf holding the
-// first finest cell of the level-top_level cell c.  If top[c] == top[c+1]
-// that leaf covers all of cell c; otherwise the leaves of cell c are exactly
-// top[c] .. top[c+1]-1 (a leaf starting before the next cell's first key
-// and reaching into it would be coarser than the cell and cover all of it).
-// A cell with as many leaves as finest cells is refined to the maximum
-// depth everywhere, and its leaves follow the keys one to one.  Only the
-// remaining, partly refined cells need a binary search over the keys.
+// The leaf holding key k: the largest index i with keys[i] <= k, and its
+// level.  top[c] locates the level-top_level cell c of k: its flags say
+// whether the cell is refined to depth D everywhere (the leaf follows from
+// the key's offset in the cell, at level D) or covered by one leaf.
+// Otherwise the cell's leaves are top[c] .. top[c+1]-1 (a leaf starting
+// before the next cell's first key and reaching into it would be coarser
+// than the cell and cover all of it), found by binary search.
 template <typename KeyT>
-__device__ __forceinline__ uint32_t find_leaf(const Tree<KeyT> &t, KeyT k) {
+__device__ __forceinline__ uint32_t find_leaf(const Tree<KeyT> &t, KeyT k, int &level) {
     const uint32_t c = (uint32_t)(k >> t.top_shift);
-    uint32_t lo = t.top[c];
-    const uint32_t nx = t.top[c + 1];
-    if (nx == lo) return lo;
-    if ((KeyT)(nx - lo) == t.cell_mask + 1) return lo + (uint32_t)(k & t.cell_mask);
-    uint32_t hi = nx;
-    while (hi - lo > 1u) {
-        const uint32_t mid = (lo + hi) >> 1;
-        if (t.keys[mid] <= k)
-            lo = mid;
-        else
-            hi = mid;
+    const uint32_t e = t.top[c];
+    uint32_t lo = e & kTopIndex;
+    if (e & kTopFull) {
+        level = t.depth;
+        return lo + (uint32_t)(k & t.cell_mask);
     }
+    if (!(e & kTopOne)) {
+        uint32_t hi = t.top[c + 1] & kTopIndex;
+        while (hi - lo > 1u) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (t.keys[mid] <= k)
+                lo = mid;
+            else
+                hi = mid;
+        }
+    }
+    level = t.levels[lo];
     return lo;
 }
 
@@ -194,11 +198,11 @@ __device__ __forceinline__ int advance_axis(bool exit, bool up, int a, int size,
     return exit ? out : c;
 }
 
-// First half of a step: the leaf that holds the probe.
+// First half of a step: the leaf that holds the probe, and its level.
 template <typename KeyT>
 __device__ __forceinline__ uint32_t ray_locate(const Ray &r, const Tree<KeyT> &t,
-                                               const uint32_t *lut) {
-    return find_leaf(t, morton(lut, r.cx, r.cy, r.cz, KeyT(0)));
+                                               const uint32_t *lut, int &level) {
+    return find_leaf(t, morton(lut, r.cx, r.cy, r.cz, KeyT(0)), level);
 }
 
 // Second half: the chord l of the ray in leaf i, and the probe moved into
@@ -206,9 +210,9 @@ __device__ __forceinline__ uint32_t ray_locate(const Ray &r, const Tree<KeyT> &t
 // not needed here, so its load (issued by the caller between the halves)
 // overlaps with this arithmetic.
 template <typename KeyT>
-__device__ __forceinline__ void ray_advance(Ray &r, const Tree<KeyT> &t, uint32_t i, double &l,
+__device__ __forceinline__ void ray_advance(Ray &r, const Tree<KeyT> &t, int level, double &l,
                                             bool &done) {
-    const int size = 1 << (t.depth - (int)t.levels[i]);
+    const int size = 1 << (t.depth - level);
     const int msk = ~(size - 1);
     const int ax = r.cx & msk, ay = r.cy & msk, az = r.cz & msk;
 
@@ -221,11 +225,12 @@ __device__ __forceinline__ void ray_advance(Ray &r, const Tree<KeyT> &t, uint32_
     // as the compare chain
     const double t_out = fmin(fmin(tfx, tfy), tfz);
 
-    l = t_out - r.t_in;
-    if (l < 0.0)
-        l = 0.0;
-    else
-        r.t_in = t_out;
+    // chord, clamped at 0: t_in moves to t_out unless rounding put t_out
+    // behind it (max(t_in, t_out) - t_in is t_out - t_in or +0; a zero
+    // chord's sign never changes a sum)
+    const double t_next = fmax(r.t_in, t_out);
+    l = t_next - r.t_in;
+    r.t_in = t_next;
     ++r.steps;
 
     const bool ex = tfx == t_out, ey = tfy == t_out, ez = tfz == t_out;
@@ -256,11 +261,12 @@ __device__ __forceinline__ int walk_ray(const Tree<KeyT> &t, const uint32_t *lut
     const int max_steps = 3 * (1 << t.depth) + 3;
     for (;;) {
         if (r.steps >= max_steps) return -1;
-        const uint32_t i = ray_locate(r, t, lut);
+        int level;
+        const uint32_t i = ray_locate(r, t, lut, level);
         const auto value = v.fetch(i);
         double l;
         bool done;
-        ray_advance(r, t, i, l, done);
+        ray_advance(r, t, level, l, done);
         v.step(value, i, l);
         if (done) break;
     }
@@ -373,12 +379,11 @@ __global__ __launch_bounds__(kBlock) void k_forward_f32k(Tree<KeyT> t, RayBatch 
 // wavefront cross the same leaves within a few steps of each other (all of
 // them share a coarse leaf at once), so the additions are first combined
 // in a per-wavefront table in LDS (after lanes of the same step that share
-// a leaf have been summed across the wavefront).  The leaf selects a set of kAggWays
-// slots (set = leaf mod kAggSets); a lane reads the set's tags at once and
-// adds into the slot holding its leaf with an LDS atomic, or claims the
-// first empty slot with compare-and-swap (a lane of the same instruction
-// that raced it to that slot with the same leaf just adds), or, when the set
-// is full, adds straight to global memory.  Every kFlushEvery steps, and
+// a leaf have been summed across the wavefront).  The leaf selects a set of
+// kAggWays slots (set = leaf mod kAggSets); a lane reads the set's tags at
+// once and adds into the slot holding its leaf, or claims the first empty
+// slot, or, when the set is full or the claim is lost to another leaf,
+// adds straight to global memory (see table_add).  Every kFlushEvery steps, and
 // when the wavefront finishes, its lanes move the table to global memory
 // with one atomic per occupied slot.  The wavefront steps in lockstep (loop
 // condition uniform over the wavefront) so that all of its lanes take part
@@ -406,17 +411,22 @@ __device__ __forceinline__ float wave_total(float v) {
 }
 
 // Adds v to the table entry of leaf (or to global memory when its set is
-// full).  Called by every lane of the wavefront with a pending value, in
-// the same instruction.  LDS atomic adds are slow when many lanes issue
-// them, so the lanes first elect one owner per slot (each writes its lane
-// number into owner[slot], the value that sticks names the owner): the
-// owner adds with a plain load and store, and only the other lanes of that
-// slot -- lanes of the same step on the same leaf -- add atomically, after
-// the owner's store.
+// full).  Called by every lane of the wavefront in the same instruction
+// (lanes without a pending value take no part).  LDS atomics are slow when
+// many lanes issue them, so the table is updated with plain loads and
+// stores, made safe by the order in which one wavefront's LDS accesses
+// complete: a lane claims an empty way by storing its leaf and reading it
+// back (the value that sticks wins; lanes of the same leaf share the way),
+// then the lanes elect one owner per slot (each stores its lane number in
+// the slot's owner cell, the value that sticks names the owner).  The owner
+// adds with a plain load and store, and only the other lanes of that slot --
+// lanes of the same step on the same leaf -- add atomically, after the
+// owner's store.
 __device__ __forceinline__ void table_add(uint32_t *tag, float *sum, uint32_t *owner,
                                           double *__restrict__ grad, uint32_t leaf, float v,
                                           bool pending, int lane) {
     int slot = -1;
+    int claim = -1;
     if (pending) {
         const int set = (int)(leaf & (kAggSets - 1)) * kAggWays;
         int empty = -1;
@@ -426,12 +436,14 @@ __device__ __forceinline__ void table_add(uint32_t *tag, float *sum, uint32_t *o
             if (tg == leaf) slot = set + way;
             if (tg == kEmpty && empty < 0) empty = set + way;
         }
-        if (slot < 0 && empty >= 0) {
-            const uint32_t old = atomicCAS(tag + empty, kEmpty, leaf);
-            if (old == kEmpty || old == leaf) slot = empty;
-        }
-        if (slot < 0) unsafeAtomicAdd(grad + leaf, (double)v);
+        claim = slot < 0 && empty >= 0 ? empty : -1;
     }
+    // claim an empty way: every claiming lane stores its leaf, the value that
+    // sticks wins; lanes of the same leaf share the claim
+    if (claim >= 0) __hip_atomic_store(tag + claim, leaf, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    if (claim >= 0 && __hip_atomic_load(tag + claim, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) == leaf)
+        slot = claim;
+    if (pending && slot < 0) unsafeAtomicAdd(grad + leaf, (double)v);
     uint32_t *cell = owner + (slot & (kOwnerSlots - 1));
     if (slot >= 0)
         __hip_atomic_store(cell, (uint32_t)lane, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -496,8 +508,9 @@ __global__ __launch_bounds__(kBlock) void k_backward(Tree<KeyT> t, RayBatch r, f
             if (active) {
                 double l;
                 bool done;
-                leaf = ray_locate(st, t, lut);
-                ray_advance(st, t, leaf, l, done);
+                int level;
+                leaf = ray_locate(st, t, lut, level);
+                ray_advance(st, t, level, l, done);
                 v = g * (float)l;
                 if (done || st.steps >= max_steps) active = false;
             }

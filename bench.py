@@ -52,8 +52,11 @@ def parse():
 
 
 def kernel_source_hash():
+    """Hash of the sources that fix what the column kernels execute: the
+    device walk, the kernels with their launch shapes, and the octree's
+    search structures."""
     h = hashlib.sha256()
-    for f in ("rt_walk.hip", "rt_abi.cpp", "rt_internal.h"):
+    for f in ("rt_ray.h", "rt_walk.hip", "rt_octree.cpp"):
         with open(os.path.join(ROOT, "paper_2605_09882_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

@@ -1,9 +1,12 @@
-// Internal interface between the C ABI (rt_abi.cpp) and the HIP kernels
-// (rt_walk.hip).  Not installed; the public interface is include/raytheia.h.
+// Internal interface between the C ABI sources (rt_abi.cpp, rt_octree.cpp)
+// and the HIP kernels.  Not installed; the public interface is
+// include/raytheia.h.
 #pragma once
 
 #include <hip/hip_runtime.h>
 #include <cstdint>
+
+struct rt_octree;
 
 namespace rt {
 
@@ -45,6 +48,18 @@ struct RayBatch {
 // Level of the top table for a tree of the given depth and leaf count.
 int top_table_level(int depth, int64_t n_leaves);
 
+// Error reporting of the C ABI: fail() records the message for
+// rt_last_error and returns status; ok() clears it and returns RT_OK;
+// device_status() maps a HIP error to RT_ERR_DEVICE (or ok()).
+int fail(int status, const char *fmt, ...);
+int ok();
+int device_status(hipError_t e, const char *what);
+
+// Checks a batch of rays (handle, pointers, counts, output strides and
+// their offset range) and fills its kernel-side description.
+int check_rays(const rt_octree *tree, const double *d_src, int64_t n_src, const double *d_dirs,
+               int64_t n_dirs, int64_t stride_src, int64_t stride_dir, RayBatch *rays);
+
 hipError_t launch_forward(const TreeView &tree, const RayBatch &rays, const void *rho,
                           int precision, double kappa, void *N, void *A, hipStream_t stream);
 
@@ -57,3 +72,9 @@ hipError_t launch_trace(const TreeView &tree, const RayBatch &rays, int32_t *ste
                         int32_t *visited, int64_t cap, hipStream_t stream);
 
 }  // namespace rt
+
+// Host handle of a built octree (opaque in the public header).
+struct rt_octree {
+    rt::TreeView view;
+    int device;
+};

@@ -13,7 +13,7 @@ visits of the forward walk (the adjoint re-walks the same ones) divided by
 the time of the pass.  The FP64 walk over the same rays is timed after the
 pass and reported beside it.
 
-Prints one JSON line.  --gpus N > 1 is refused: this build runs on one GPU.
+Prints one JSON line.  --gpus N > 1 is refused: the library runs on one GPU.
 """
 
 import argparse

@@ -18,6 +18,9 @@ Functions and the passages they follow:
                  I = sum_k f_k r_k (sec. 2.3).
   columns        all (source, direction) rays, N and exp(-kappa N) (sec. 2.1).
   gradient       dL/drho_k = sum over rays of dL/dN * r_k (N is linear in rho).
+  shielding      several fields per leaf: per-ray N_H and line optical depths
+                 tau (sec. 2.4), per-source escape probabilities beta
+                 (sec. 2.4) and effective visual extinction A_V,eff (sec. 3).
 """
 
 import ctypes
@@ -65,6 +68,10 @@ def _bind(lib):
                                 P, P, P, P, P, P, P, P]
     lib.orc_gradient.restype = ctypes.c_int
     lib.orc_gradient.argtypes = [P, P, i64, ctypes.c_int, P, i64, P, i64, P, P]
+    D = ctypes.c_double
+    lib.orc_shielding.restype = ctypes.c_int
+    lib.orc_shielding.argtypes = [P, P, i64, ctypes.c_int, P, ctypes.c_int, P, i64, P, i64, D, P,
+                                  D, P, P, D, D, P, P, P]
     return lib
 
 
@@ -197,3 +204,49 @@ def gradient(tree, src, dirs, g, lib=None):
     if st != OK:
         raise RuntimeError(f"orc_gradient failed: {st}")
     return grad
+
+
+def shielding(tree, fields, src, dirs, length=1.0, temp=None, vturb=0.0, line_A=(), line_nu=(),
+              gamma=3.02, av0=6.29e-22, rays=True, threads=1, lib=None):
+    """Per-source A_V,eff and escape probabilities, and optionally the per-ray
+    values, for leaf fields [n, K] (field 0 = n_H, fields 1.. = the
+    population terms of the lines (line_A[f-1], line_nu[f-1])).  Returns a
+    dict: rays [S, Dn, K] (N_H, then tau per line) if rays, av_eff [S],
+    beta [S, K-1], status.  threads > 1 splits the sources over threads."""
+    lib = lib or load()
+    keys = _c(tree.keys, np.uint64)
+    levels = _c(tree.levels, np.uint8)
+    fields = _c(fields, np.float64)
+    if fields.ndim == 1:
+        fields = fields[:, None]
+    n, K = fields.shape
+    assert n == keys.shape[0]
+    src = _c(src, np.float64).reshape(-1, 3)
+    dirs = _c(dirs, np.float64).reshape(-1, 3)
+    S, Dn = src.shape[0], dirs.shape[0]
+    T = None if temp is None else _c(np.broadcast_to(temp, (S,)), np.float64)
+    lA = _c(line_A, np.float64) if K > 1 else None
+    lnu = _c(line_nu, np.float64) if K > 1 else None
+    if K > 1:
+        assert lA.shape == (K - 1,) and lnu.shape == (K - 1,)
+    out = {"av_eff": np.empty(S), "beta": np.empty((S, K - 1))}
+    if rays:
+        out["rays"] = np.empty((S, Dn, K))
+
+    def run(lo, hi):
+        return lib.orc_shielding(_p(keys), _p(levels), n, tree.depth, _p(fields), K,
+                                 _p(src[lo:hi]), hi - lo, _p(dirs), Dn, float(length),
+                                 _p(None if T is None else T[lo:hi]), float(vturb), _p(lA), _p(lnu),
+                                 float(gamma), float(av0),
+                                 _p(out["rays"][lo:hi]) if rays else None,
+                                 _p(out["av_eff"][lo:hi]), _p(out["beta"][lo:hi]))
+
+    if threads <= 1 or S < 2 * threads:
+        results = [run(0, S)]
+    else:
+        bounds = np.linspace(0, S, threads + 1).astype(np.int64)
+        with ThreadPoolExecutor(threads) as ex:
+            results = list(ex.map(lambda ab: run(int(ab[0]), int(ab[1])),
+                                  zip(bounds[:-1], bounds[1:])))
+    out["status"] = next((st for st in results if st != OK), OK)
+    return out

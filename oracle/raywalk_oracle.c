@@ -34,6 +34,11 @@
  *
  * Directions: HEALPix RING pixel centres (Gorski et al. 2005, as used in
  * sec. 2.1), written here from the ring geometry.
+ *
+ * Several fields per leaf (orc_shielding): the same walk integrates every
+ * field; the per-ray columns give the line optical depths and the per-source
+ * escape probabilities of sec. 2.4 and the effective visual extinction of
+ * sec. 3.
  */
 #include <math.h>
 #include <stdint.h>
@@ -354,5 +359,120 @@ int orc_gradient(const uint64_t *keys, const uint8_t *levels, int64_t n, int dep
     free(vis);
     free(chords);
     free(zero);
+    return status;
+}
+
+/* ------------------------------------------------------------------ */
+/* Several fields per leaf: line optical depths, escape probabilities  */
+/* and the effective visual extinction                                 */
+/* ------------------------------------------------------------------ */
+
+/* CGS constants (CODATA 2018): Boltzmann constant, proton mass, speed of light. */
+#define ORC_KB 1.380649e-16
+#define ORC_MP 1.67262192369e-24
+#define ORC_C 2.99792458e10
+
+/* Direction-dependent integrals of several leaf fields, and their
+ * per-source reductions over directions (paper sec. 2.4 and sec. 3).
+ *
+ * fields is [n][K]: per leaf, field 0 is the hydrogen number density n_H and
+ * field f = 1 .. K-1 is the level-population term [n_j g_i / g_j - n_i] of
+ * line f, whose Einstein coefficient and frequency are lineA[f-1] and
+ * linenu[f-1].  For the ray (s, d) of walk_ray (box units):
+ *   I_f   = sum over visited leaves k of fields[k][f] * r_k, in visiting
+ *           order, I = I + F r (the discrete integral of sec. 2.3);
+ *   N_f   = length * I_f, the column in cm^-2 for a box edge of length cm;
+ *   du    = sqrt(8 kB T_s / (pi m_p) + vturb^2), the rms of thermal and
+ *           turbulent speed at the source (sec. 2.4);
+ *   tau_f = coef_f * N_f / du with coef_f = A c^3 / (8 pi nu^3) (discretised
+ *           line optical depth, sec. 2.4).
+ * Per source, over its Dn directions d = 0 .. Dn-1:
+ *   beta_f = (1/Dn) sum_d (1 - exp(-tau_f)) / tau_f, the escape probability
+ *            (sec. 2.4); the term is its limit 1 at tau = 0 and is evaluated
+ *            as -expm1(-tau) / tau otherwise, for every sign of tau;
+ *   AV_eff = -(1/gamma) ln((1/Dn) sum_d exp(-gamma av0 N_H)) (sec. 3), evaluated
+ *            with x_d = gamma av0 N_H,d and x_min = min_d x_d as
+ *            (x_min - ln((1/Dn) sum_d exp(-(x_d - x_min)))) / gamma, which is
+ *            the same number but does not underflow for large columns.
+ * Outputs, each may be NULL: rays [S][Dn][K] with N_H at f = 0 and tau_f at
+ * f >= 1; av_eff [S]; beta [S][K-1].  temp [S] (kelvin) is needed when
+ * K > 1.  A source with an invalid ray, or with du not finite and > 0, gets
+ * NaN in all its outputs, and the first such error is returned. */
+int orc_shielding(const uint64_t *keys, const uint8_t *levels, int64_t n, int depth,
+                  const double *fields, int K, const double *src, int64_t S,
+                  const double *dirs, int64_t Dn, double length, const double *temp,
+                  double vturb, const double *lineA, const double *linenu, double gamma,
+                  double av0, double *rays, double *av_eff, double *beta)
+{
+    const double pi = 3.14159265358979323846;
+    if (K < 1 || !fields || (K > 1 && (!temp || !lineA || !linenu)) || S < 0 || Dn < 1)
+        return ORC_ERR_ARG;
+    int64_t cap = 3 * ((int64_t)1 << depth) + 3;
+    int64_t *vis = (int64_t *)malloc(sizeof(int64_t) * cap);
+    double *chords = (double *)malloc(sizeof(double) * cap);
+    double *zero = (double *)calloc((size_t)n, sizeof(double));
+    double *I = (double *)malloc(sizeof(double) * K);
+    double *coef = (double *)malloc(sizeof(double) * K);
+    double *bsum = (double *)malloc(sizeof(double) * K);
+    double *x = (double *)malloc(sizeof(double) * Dn);
+    if (!vis || !chords || !zero || !I || !coef || !bsum || !x) {
+        free(vis); free(chords); free(zero); free(I); free(coef); free(bsum); free(x);
+        return ORC_ERR_ARG;
+    }
+    for (int f = 1; f < K; ++f) {
+        const double nu = linenu[f - 1];
+        coef[f] = lineA[f - 1] * (ORC_C * ORC_C * ORC_C) / (8.0 * pi * (nu * nu * nu));
+    }
+    int status = ORC_OK;
+    for (int64_t s = 0; s < S; ++s) {
+        int bad = 0;
+        double du = 1.0;
+        if (K > 1) {
+            du = sqrt(8.0 * ORC_KB * temp[s] / (pi * ORC_MP) + vturb * vturb);
+            if (!(du > 0.0 && isfinite(du))) {
+                bad = 1;
+                if (status == ORC_OK) status = ORC_ERR_RANGE;
+            }
+        }
+        for (int f = 0; f < K; ++f) bsum[f] = 0.0;
+        for (int64_t d = 0; d < Dn && !bad; ++d) {
+            ray_out o;
+            int st = walk_ray(keys, levels, zero, NULL, n, depth, src + 3 * s, dirs + 3 * d, &o,
+                              vis, chords, cap);
+            if (st != ORC_OK) {
+                bad = 1;
+                if (status == ORC_OK) status = st;
+                break;
+            }
+            for (int f = 0; f < K; ++f) I[f] = 0.0;
+            for (int64_t j = 0; j < o.steps; ++j)
+                for (int f = 0; f < K; ++f) I[f] = I[f] + fields[vis[j] * K + f] * chords[j];
+            const double nh = length * I[0];
+            x[d] = gamma * av0 * nh;
+            if (rays) rays[(s * Dn + d) * K] = nh;
+            for (int f = 1; f < K; ++f) {
+                const double tau = coef[f] * (length * I[f]) / du;
+                bsum[f] += tau == 0.0 ? 1.0 : -expm1(-tau) / tau;
+                if (rays) rays[(s * Dn + d) * K + f] = tau;
+            }
+        }
+        if (bad) {
+            if (rays)
+                for (int64_t j = 0; j < Dn * K; ++j) rays[s * Dn * K + j] = NAN;
+            if (av_eff) av_eff[s] = NAN;
+            if (beta)
+                for (int f = 1; f < K; ++f) beta[s * (K - 1) + f - 1] = NAN;
+            continue;
+        }
+        double xmin = x[0];
+        for (int64_t d = 1; d < Dn; ++d)
+            if (x[d] < xmin) xmin = x[d];
+        double sum = 0.0;
+        for (int64_t d = 0; d < Dn; ++d) sum += exp(-(x[d] - xmin));
+        if (av_eff) av_eff[s] = (xmin - log(sum / (double)Dn)) / gamma;
+        if (beta)
+            for (int f = 1; f < K; ++f) beta[s * (K - 1) + f - 1] = bsum[f] / (double)Dn;
+    }
+    free(vis); free(chords); free(zero); free(I); free(coef); free(bsum); free(x);
     return status;
 }

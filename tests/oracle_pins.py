@@ -13,6 +13,8 @@ Which pin covers which oracle function:
                 pin_deep_tree, pin_kahan_compensation
   columns       pin_linearity_and_refinement, pin_columns_consistency, pin_kahan_bound
   gradient      pin_gradient
+  shielding     pin_shielding_integrals, pin_line_depth_constants,
+                pin_escape_probability, pin_av_eff, pin_shielding_edge_cases
 """
 
 import os
@@ -424,6 +426,149 @@ def pin_gradient(orc, lib):
         assert abs(fd - grad[k]) <= 1e-8 * scale
 
 
+# ---------------------------------------------------------------- several fields per leaf
+
+AXES = np.array([[1, 0, 0], [-1, 0, 0], [0, 1, 0], [0, -1, 0], [0, 0, 1], [0, 0, -1]], float)
+# CGS constants (CODATA 2018) and the speed of light: A = 8 pi and nu = c make
+# the line prefactor A c^3 / (8 pi nu^3) exactly 1 (the same roundings in
+# numerator and denominator); T = 0 and vturb = 1 make du = 1.
+C_LIGHT = 2.99792458e10
+UNIT_LINE = dict(line_A=8.0 * np.pi, line_nu=C_LIGHT)
+
+
+def _unit_lines(k):
+    return dict(line_A=[UNIT_LINE["line_A"]] * k, line_nu=[UNIT_LINE["line_nu"]] * k)
+
+
+def pin_shielding_integrals(orc, lib):
+    """With a unit line prefactor and du = 1, the per-ray values are the
+    columns of each field alone (the single-field walk, pinned above), times
+    the length unit, bit for bit."""
+    t = W.random_octree(4, 0.45, 201, min_level=1)
+    rng = np.random.default_rng(202)
+    F = np.stack([t.rho, rng.standard_normal(t.n), rng.random(t.n) * 3.0], 1)
+    src = W.random_points(9, 203)
+    dirs = orc.healpix_ring(2, lib=lib)
+    L = 3.0
+    out = orc.shielding(t, F, src, dirs, length=L, temp=np.zeros(len(src)), vturb=1.0,
+                        **_unit_lines(2), lib=lib)
+    assert out["status"] == orc.OK
+    for f in range(3):
+        N = orc.columns(t, src, dirs, rho=F[:, f], lib=lib)["N"]
+        assert np.array_equal(out["rays"][:, :, f], L * N), f
+
+
+def pin_line_depth_constants(orc, lib):
+    """tau = A c^3 / (8 pi nu^3) N / du: exactly N for the unit prefactor;
+    linear in A, falling as nu^-3, and 1/du with du the quadrature sum of
+    the mean thermal speed sqrt(8 kB T / (pi m_p)) and vturb (for protons at
+    100 K the mean speed is 1.450 km/s)."""
+    t = W.uniform_octree(2, np.full(64, 1.0))
+    src = np.array([[0.5, 0.5, 0.5]])
+    N_ref = 0.5 * 7.0  # column of field 1 along an axis from the centre, length 7
+    F = np.stack([np.ones(64), np.ones(64)], 1)
+
+    def tau(A, nu, T, vt):
+        o = orc.shielding(t, F, src, AXES[:1], length=7.0, temp=[T], vturb=vt, line_A=[A],
+                          line_nu=[nu], lib=lib)
+        assert o["status"] == orc.OK
+        return o["rays"][0, 0, 1]
+
+    A1, nu1 = UNIT_LINE["line_A"], UNIT_LINE["line_nu"]
+    assert tau(A1, nu1, 0.0, 1.0) == N_ref
+    base = tau(7.2e-8, 1.15e11, 0.0, 1.0e5)
+    assert abs(tau(2 * 7.2e-8, 1.15e11, 0.0, 1.0e5) / base - 2.0) <= 1e-15
+    assert abs(tau(7.2e-8, 2 * 1.15e11, 0.0, 1.0e5) / base - 0.125) <= 1e-15
+    assert abs(tau(7.2e-8, 1.15e11, 0.0, 4.0e5) / base - 0.25) <= 1e-15
+    du_thermal = N_ref / tau(A1, nu1, 100.0, 0.0)
+    assert abs(du_thermal - 1.450e5) <= 0.001e5, du_thermal
+    # quadrature: thermal speed equal to vturb gives sqrt(2) vturb
+    du_both = N_ref / tau(A1, nu1, 100.0, du_thermal)
+    assert abs(du_both / (np.sqrt(2.0) * du_thermal) - 1.0) <= 1e-14
+
+
+def _axis_beta(orc, lib, value, length=2.0):
+    """beta at the centre of a uniform field: all six axis rays see
+    tau = value * 0.5 * length (unit prefactor, du = 1)."""
+    t = W.uniform_octree(2, np.ones(64))
+    F = np.stack([np.ones(64), np.full(64, value)], 1)
+    o = orc.shielding(t, F, [[0.5, 0.5, 0.5]], AXES, length=length, temp=[0.0], vturb=1.0,
+                      **_unit_lines(1), lib=lib)
+    assert o["status"] == orc.OK
+    assert np.all(o["rays"][0, :, 1] == value * 0.5 * length)
+    return o["beta"][0, 0]
+
+
+def pin_escape_probability(orc, lib):
+    """beta = mean over directions of (1 - e^-tau) / tau: 1 - 1/e at tau = 1,
+    e - 1 at tau = -1 (inverted populations), 1 at tau = 0, 1 - tau/2 for
+    tiny tau (the naive quotient loses digits there), 1/tau for large tau,
+    and the average of two directions with different depths."""
+    assert abs(_axis_beta(orc, lib, 1.0) - 0.6321205588285577) <= 2e-16
+    assert abs(_axis_beta(orc, lib, -1.0) - 1.718281828459045) <= 4e-16
+    assert _axis_beta(orc, lib, 0.0) == 1.0
+    b = _axis_beta(orc, lib, 1e-12)
+    assert abs(b - (1.0 - 0.5e-12)) <= 2e-16
+    assert abs(_axis_beta(orc, lib, 800.0) - 1.0 / 800.0) <= 1e-18
+    # field 1 only in x < 1/2: from (1/2, 1/2, 1/2) the +x ray sees tau = 0,
+    # the -x ray tau = 2 (length 4, chord 1/2)
+    t = W.uniform_octree(1, np.ones(8))
+    x_low = (np.arange(8) & 1) == 0  # Morton bit 0 is x
+    F = np.stack([np.ones(8), np.where(x_low, 1.0, 0.0)], 1)
+    o = orc.shielding(t, F, [[0.5, 0.5, 0.5]], AXES[:2], length=4.0, temp=[0.0], vturb=1.0,
+                      **_unit_lines(1), lib=lib)
+    assert abs(o["beta"][0, 0] - 0.7161661791908468) <= 2e-16
+
+
+def pin_av_eff(orc, lib):
+    """AV_eff = -(1/gamma) ln(mean_d exp(-gamma av0 N_d)): av0 N when all
+    directions agree (also where exp(-gamma av0 N) underflows), ln 2 / gamma
+    for one clear and one opaque direction, between the smallest and the
+    mean av0 N in general, and the mean in the limit gamma -> 0."""
+    gamma, av0 = 3.02, 6.29e-22
+    t = W.uniform_octree(2, np.ones(64))
+    centre = [[0.5, 0.5, 0.5]]
+    for nh in (1.0, 1e21, 3e24):  # gamma av0 N = 1.9e-21, 0.95, 2850
+        o = orc.shielding(t, np.full(64, nh), centre, AXES, length=2.0, gamma=gamma, av0=av0,
+                          lib=lib)
+        want = av0 * nh  # N = nh * 0.5 * 2
+        assert o["status"] == orc.OK
+        assert abs(o["av_eff"][0] - want) <= 1e-14 * want, (nh, o["av_eff"][0], want)
+    t1 = W.uniform_octree(1, np.ones(8))
+    x_low = (np.arange(8) & 1) == 0
+    o = orc.shielding(t1, np.where(x_low, 1e26, 0.0), centre, AXES[:2], gamma=gamma, av0=av0,
+                      lib=lib)
+    assert abs(o["av_eff"][0] - np.log(2.0) / gamma) <= 1e-15
+    tr = W.random_octree(4, 0.45, 211, min_level=1)
+    nh = tr.rho * 1e22
+    src = W.random_points(20, 212)
+    dirs = orc.healpix_ring(2, lib=lib)
+    o = orc.shielding(tr, nh, src, dirs, gamma=gamma, av0=av0, lib=lib)
+    av = av0 * o["rays"][:, :, 0]
+    assert np.all(o["av_eff"] >= av.min(1) * (1 - 1e-14))
+    assert np.all(o["av_eff"] <= av.mean(1) * (1 + 1e-14))
+    assert np.all(o["av_eff"] < av.mean(1))  # strict: the columns differ
+    o = orc.shielding(tr, nh, src, dirs, gamma=1e-9, av0=av0, lib=lib)
+    assert np.all(np.abs(o["av_eff"] / av.mean(1) - 1.0) <= 1e-6)
+
+
+def pin_shielding_edge_cases(orc, lib):
+    """A source outside the box, or du not > 0, gives NaN for that source
+    only and an error; an empty field gives AV_eff = 0 and beta = 1."""
+    t = W.uniform_octree(2, np.ones(64))
+    F = np.stack([np.zeros(64), np.zeros(64)], 1)
+    src = np.array([[0.3, 0.3, 0.3], [1.0, 0.5, 0.5], [0.6, 0.6, 0.6]])
+    o = orc.shielding(t, F, src, AXES, temp=[10.0, 10.0, 10.0], vturb=0.0, **_unit_lines(1),
+                      lib=lib)
+    assert o["status"] == orc.ERR_RANGE
+    assert np.all(np.isnan(o["rays"][1])) and np.isnan(o["av_eff"][1]) and np.isnan(o["beta"][1, 0])
+    assert np.all(o["av_eff"][[0, 2]] == 0.0) and np.all(o["beta"][[0, 2], 0] == 1.0)
+    o = orc.shielding(t, F, src[[0, 2]], AXES, temp=[0.0, 10.0], vturb=0.0, **_unit_lines(1),
+                      lib=lib)
+    assert o["status"] == orc.ERR_RANGE
+    assert np.isnan(o["av_eff"][0]) and o["av_eff"][1] == 0.0
+
+
 ALL_PINS = [
     pin_healpix_golden_nside1,
     pin_healpix_structure,
@@ -441,4 +586,9 @@ ALL_PINS = [
     pin_kahan_compensation,
     pin_kahan_bound,
     pin_gradient,
+    pin_shielding_integrals,
+    pin_line_depth_constants,
+    pin_escape_probability,
+    pin_av_eff,
+    pin_shielding_edge_cases,
 ]

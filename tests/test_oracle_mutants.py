@@ -45,6 +45,17 @@ MUTANTS = {
     "non_exit_axis_frozen": ("double x = fma(m[a], t_out, Q[a]) * scale;",
                              "double x = (double)p[a];"),
     "tiling_gap_ignored": ("if (keys[i] != expect) return ORC_ERR_TILING;", ""),
+    "fields_plane_major": ("I[f] = I[f] + fields[vis[j] * K + f] * chords[j];",
+                           "I[f] = I[f] + fields[f * n + vis[j]] * chords[j];"),
+    "length_unit_dropped": ("const double nh = length * I[0];", "const double nh = I[0];"),
+    "line_nu_squared": ("(8.0 * pi * (nu * nu * nu))", "(8.0 * pi * (nu * nu))"),
+    "line_drops_8pi": ("(8.0 * pi * (nu * nu * nu))", "(nu * nu * nu)"),
+    "du_no_turbulence": ("/ (pi * ORC_MP) + vturb * vturb);", "/ (pi * ORC_MP));"),
+    "du_no_pi": ("/ (pi * ORC_MP) + vturb * vturb);", "/ ORC_MP + vturb * vturb);"),
+    "beta_naive_quotient": ("1.0 : -expm1(-tau) / tau;", "1.0 : (1.0 - exp(-tau)) / tau;"),
+    "beta_zero_depth_term": ("tau == 0.0 ? 1.0 :", "tau == 0.0 ? 0.0 :"),
+    "av_eff_shift_lost": ("(xmin - log(sum / (double)Dn)) / gamma", "(-log(sum / (double)Dn)) / gamma"),
+    "av_eff_mean_not_sum": ("log(sum / (double)Dn)", "log(sum)"),
 }
 
 BATTERY = """

@@ -171,6 +171,58 @@ int rt_columns_trace(const rt_octree *tree, const double *d_src, int64_t n_src,
                      int64_t stride_src, int64_t stride_dir, const int64_t *d_sample,
                      int64_t n_sample, int32_t *d_visited, int64_t cap, void *stream);
 
+/* ---------------------------------------------------------------------
+ * Several fields per leaf: line optical depths, escape probabilities and
+ * the effective visual extinction (sec. 2.4 and sec. 3).
+ * ------------------------------------------------------------------- */
+
+/* Largest number of leaf fields of one rt_shielding call. */
+#define RT_MAX_FIELDS 8
+
+/* One walk per ray (s, d) integrates K = n_fields leaf fields at once,
+ * I_f = sum_k F[k][f] r_k (FP64, visiting order, the traversal of
+ * rt_columns), and the results are reduced over the n_dirs directions of
+ * each source.  Field 0 is the hydrogen number density n_H (cm^-3); field
+ * f = 1 .. K-1 is the level-population term [n_j g_i / g_j - n_i] (cm^-3)
+ * of line f (sec. 2.4).  With N_f = length * I_f (cm^-2):
+ *   du(s)    = sqrt(8 kB T_s / (pi m_p) + vturb^2), kB = 1.380649e-16 erg/K,
+ *              m_p = 1.67262192369e-24 g (the rms speed of sec. 2.4);
+ *   tau_f    = A_f c^3 / (8 pi nu_f^3) * N_f / du, c = 2.99792458e10 cm/s
+ *              (the discretised line optical depth of sec. 2.4);
+ *   beta_f(s) = (1/n_dirs) sum_d (1 - exp(-tau_f)) / tau_f, with the term 1
+ *              at tau = 0, for either sign of tau (escape probability,
+ *              sec. 2.4);
+ *   av_eff(s) = -(1/gamma) ln((1/n_dirs) sum_d exp(-gamma av0 N_0))
+ *              (effective visual extinction, sec. 3; evaluated without
+ *              underflow for large columns).
+ *   d_fields  device f64 [n_leaves][n_fields] (a leaf's fields contiguous);
+ *   n_fields  K, 1..RT_MAX_FIELDS;
+ *   d_src, d_dirs as for rt_columns;
+ *   length    edge of the unit box in cm;
+ *   d_temp    device f64 [n_src], source gas temperatures in K; required
+ *             when n_fields > 1, else ignored (may be NULL);
+ *   vturb     turbulent speed in cm/s;
+ *   line_A, line_nu  host f64 [n_fields - 1], Einstein A (s^-1) and line
+ *             frequency (Hz) of each line; required when n_fields > 1;
+ *   gamma, av0  dust attenuation factor and A_V per unit column (the paper
+ *             uses 3.02 and 6.29e-22 mag cm^2);
+ *   d_rays    device output or NULL, f64 [n_fields][n_dirs][n_src]: N_0 in
+ *             plane 0 and tau_f in plane f;
+ *   d_av_eff  device output or NULL, f64 [n_src];
+ *   d_beta    device output or NULL, f64 [n_fields - 1][n_src] (ignored
+ *             when n_fields = 1).
+ * One lane walks all directions of one source, so n_src should be large
+ * (>= 10^5) to fill the GPU.  A source outside [0,1)^3, an invalid
+ * direction, or du not finite and > 0 gives NaN in all outputs of that
+ * source.  Errors: RT_ERR_ARG (null pointers, counts out of range, output
+ * size overflow, non-finite length/gamma/av0/vturb/A, nu <= 0, gamma = 0),
+ * RT_ERR_DEVICE. */
+int rt_shielding(const rt_octree *tree, const double *d_fields, int n_fields, const double *d_src,
+                 int64_t n_src, const double *d_dirs, int64_t n_dirs, double length,
+                 const double *d_temp, double vturb, const double *line_A, const double *line_nu,
+                 double gamma, double av0, double *d_rays, double *d_av_eff, double *d_beta,
+                 void *stream);
+
 #ifdef __cplusplus
 }
 #endif

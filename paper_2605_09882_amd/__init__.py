@@ -1,15 +1,17 @@
 """MI355X reverse ray walk through a leaf-only linear octree.
 
 Column densities N = sum_k rho_k r_k and attenuations exp(-kappa N) for every
-(source point, HEALPix direction) pair, computed by hand-written HIP kernels
-for gfx950 behind the C ABI of include/raytheia.h (method: Zhu et al.,
-RAYTHEIA, sec. 2).  ``_abi`` is the ctypes binding of that ABI; ``raywalk``
+(source point, HEALPix direction) pair, their adjoint, and -- from one walk
+over several leaf fields -- line optical depths, escape probabilities and the
+effective visual extinction, computed by hand-written HIP kernels for gfx950
+behind the C ABI of include/raytheia.h (method: Zhu et al., RAYTHEIA,
+sec. 2-3).  ``_abi`` is the ctypes binding of that ABI; ``raywalk``
 passes torch device tensors and the current stream to it.
 """
 
 from . import _abi
 from .raywalk import (Octree, RayColumns, columns, columns_backward, columns_trace, healpix_dirs,
-                      healpix_npix, ray_columns)
+                      healpix_npix, ray_columns, shielding)
 
 __all__ = [
     "_abi",
@@ -21,4 +23,5 @@ __all__ = [
     "healpix_dirs",
     "healpix_npix",
     "ray_columns",
+    "shielding",
 ]

@@ -38,7 +38,10 @@ EXPORTS = (
     "rt_columns",
     "rt_columns_backward",
     "rt_columns_trace",
+    "rt_shielding",
 )
+
+RT_MAX_FIELDS = 8
 
 
 class RtError(RuntimeError):
@@ -75,6 +78,7 @@ def load(path=None):
         "rt_columns": (I32, [V, P, I32, P, I64, P, I64, D, P, P, I64, I64, V]),
         "rt_columns_backward": (I32, [V, P, I64, P, I64, D, P, P, P, I64, I64, P, V]),
         "rt_columns_trace": (I32, [V, P, I64, P, I64, P, P, I64, I64, P, I64, P, I64, V]),
+        "rt_shielding": (I32, [V, P, I32, P, I64, P, I64, D, P, D, P, P, D, D, P, P, P, V]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -157,3 +161,12 @@ def rt_columns_trace(handle, src_ptr, n_src, dirs_ptr, n_dirs, steps_ptr, hash_p
                                    hash_ptr, int(stride_src), int(stride_dir), sample_ptr,
                                    int(n_sample), visited_ptr, int(cap), stream),
            "rt_columns_trace")
+
+
+def rt_shielding(handle, fields_ptr, n_fields, src_ptr, n_src, dirs_ptr, n_dirs, length, temp_ptr,
+                 vturb, line_A_ptr, line_nu_ptr, gamma, av0, rays_ptr, av_eff_ptr, beta_ptr,
+                 stream):
+    _check(load().rt_shielding(handle, fields_ptr, int(n_fields), src_ptr, int(n_src), dirs_ptr,
+                               int(n_dirs), float(length), temp_ptr, float(vturb), line_A_ptr,
+                               line_nu_ptr, float(gamma), float(av0), rays_ptr, av_eff_ptr,
+                               beta_ptr, stream), "rt_shielding")

@@ -205,4 +205,52 @@ int rt_columns_trace(const rt_octree *tree, const double *d_src, int64_t n_src,
     return device_status(e, "trace walk launch");
 }
 
+// ---------------------------------------------------------------------
+// Several fields per leaf
+// ---------------------------------------------------------------------
+
+int rt_shielding(const rt_octree *tree, const double *d_fields, int n_fields, const double *d_src,
+                 int64_t n_src, const double *d_dirs, int64_t n_dirs, double length,
+                 const double *d_temp, double vturb, const double *line_A, const double *line_nu,
+                 double gamma, double av0, double *d_rays, double *d_av_eff, double *d_beta,
+                 void *stream) {
+    rt::RayBatch rays;
+    // the per-ray output is [n_fields][n_dirs][n_src]: strides 1 and n_src
+    int st = check_rays(tree, d_src, n_src, d_dirs, n_dirs, 1, n_src, &rays);
+    if (st != RT_OK) return st;
+    if (n_fields < 1 || n_fields > RT_MAX_FIELDS)
+        return fail(RT_ERR_ARG, "n_fields %d not in 1..%d", n_fields, RT_MAX_FIELDS);
+    if (!d_fields) return fail(RT_ERR_ARG, "null fields");
+    if (n_src * n_dirs > INT64_MAX / n_fields) return fail(RT_ERR_ARG, "per-ray output size overflows");
+    if (!std::isfinite(length) || !std::isfinite(gamma) || gamma == 0.0 || !std::isfinite(av0))
+        return fail(RT_ERR_ARG, "length, gamma and av0 must be finite and gamma non-zero");
+    rt::ShieldingParams p;
+    p.length = length;
+    p.temp = d_temp;
+    p.vturb = vturb;
+    p.gamma = gamma;
+    p.gamma_av0 = gamma * av0;
+    for (int f = 0; f < rt::kMaxFields; ++f) p.coef[f] = 0.0;
+    if (n_fields > 1) {
+        if (!d_temp || !line_A || !line_nu)
+            return fail(RT_ERR_ARG, "lines need source temperatures, line_A and line_nu");
+        if (!std::isfinite(vturb)) return fail(RT_ERR_ARG, "vturb not finite");
+        const double c = 2.99792458e10;  // speed of light, cm/s
+        const double pi = 3.14159265358979323846;
+        for (int f = 1; f < n_fields; ++f) {
+            const double A = line_A[f - 1], nu = line_nu[f - 1];
+            if (!std::isfinite(A) || !std::isfinite(nu) || !(nu > 0.0))
+                return fail(RT_ERR_ARG, "line %d: A must be finite and nu finite and > 0", f);
+            // the prefactor of the discretised line optical depth (sec. 2.4)
+            p.coef[f] = A * (c * c * c) / (8.0 * pi * (nu * nu * nu));
+            if (!std::isfinite(p.coef[f])) return fail(RT_ERR_ARG, "line %d: prefactor overflows", f);
+        }
+    }
+    if (!d_rays && !d_av_eff && !d_beta) return ok();  // nothing requested
+    hipError_t e = rt::launch_shielding(tree->view, rays, d_fields, n_fields, p, d_rays, d_av_eff,
+                                        n_fields > 1 ? d_beta : nullptr,
+                                        static_cast<hipStream_t>(stream));
+    return device_status(e, "shielding walk launch");
+}
+
 }  // extern "C"

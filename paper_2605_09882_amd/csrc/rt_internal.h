@@ -67,6 +67,23 @@ hipError_t launch_backward(const TreeView &tree, const RayBatch &rays, double ka
                            const float *gN, const float *gA, const float *A, double *grad,
                            hipStream_t stream);
 
+// Several fields per leaf (rt_shielding): at most kMaxFields fields, field 0
+// the hydrogen density, fields 1.. the population terms of the lines.
+constexpr int kMaxFields = 8;
+
+struct ShieldingParams {
+    double length;            // box edge in cm
+    const double *temp;       // device, [n_src] source temperatures (K), used when K > 1
+    double vturb;             // turbulent speed, cm/s
+    double gamma;             // dust attenuation factor
+    double gamma_av0;         // gamma * av0
+    double coef[kMaxFields];  // coef[f] = A_f c^3 / (8 pi nu_f^3) for f = 1 .. K-1
+};
+
+hipError_t launch_shielding(const TreeView &tree, const RayBatch &rays, const double *fields,
+                            int n_fields, const ShieldingParams &p, double *ray_out,
+                            double *av_eff, double *beta, hipStream_t stream);
+
 hipError_t launch_trace(const TreeView &tree, const RayBatch &rays, int32_t *steps,
                         uint64_t *hash, const int64_t *sample, int64_t n_sample,
                         int32_t *visited, int64_t cap, hipStream_t stream);

@@ -166,6 +166,60 @@ def columns_trace(tree, src, dirs, sample=None, cap=0):
     return steps.t(), h.t(), visited
 
 
+def shielding(tree, fields, src, dirs, length, temp=None, vturb=0.0, line_A=(), line_nu=(),
+              gamma=3.02, av0=6.29e-22, rays=False, av_eff=True, beta=True):
+    """Line optical depths, escape probabilities and the effective visual
+    extinction (sec. 2.4, sec. 3) from one walk per ray over K leaf fields.
+
+    fields: device float64 [n_leaves, K] (field 0 = n_H, field f >= 1 = the
+    population term of line f with Einstein A line_A[f-1] and frequency
+    line_nu[f-1]); src [S, 3], dirs [Dn, 3]; length = box edge in cm;
+    temp [S] source temperatures in K (needed when K > 1); vturb in cm/s.
+    Returns a dict with "av_eff" [S], "beta" [S, K-1] (views over
+    line-major buffers) and, if rays, "rays" [S, Dn, K] (N_H, then tau per
+    line; a view over the [K, Dn, S] buffer)."""
+    dev = tree.device
+    if not torch.is_tensor(fields) or fields.dtype != torch.float64 or not fields.is_cuda:
+        raise TypeError("fields must be a float64 device tensor")
+    if fields.ndim == 1:
+        fields = fields[:, None]
+    fields = fields.contiguous()
+    if fields.shape[0] != tree.n:
+        raise ValueError("fields must hold one row per leaf")
+    K = int(fields.shape[1])
+    src = _as_dev(src, torch.float64, dev, 3)
+    dirs = _as_dev(dirs, torch.float64, dev, 3)
+    S, Dn = src.shape[0], dirs.shape[0]
+    T = None
+    lA = lnu = None
+    if K > 1:
+        if temp is None:
+            raise ValueError("lines need source temperatures")
+        T = torch.as_tensor(np.broadcast_to(np.asarray(temp, dtype=np.float64), (S,))
+                            if not torch.is_tensor(temp) else temp)
+        T = T.to(device=dev, dtype=torch.float64).contiguous()
+        lA = np.ascontiguousarray(line_A, dtype=np.float64)
+        lnu = np.ascontiguousarray(line_nu, dtype=np.float64)
+        if lA.shape != (K - 1,) or lnu.shape != (K - 1,):
+            raise ValueError(f"line_A and line_nu need {K - 1} entries")
+    out_rays = torch.empty((K, Dn, S), dtype=torch.float64, device=dev) if rays else None
+    out_av = torch.empty(S, dtype=torch.float64, device=dev) if av_eff else None
+    out_beta = torch.empty((K - 1, S), dtype=torch.float64, device=dev) if beta and K > 1 else None
+    _abi.rt_shielding(tree.handle, fields.data_ptr(), K, src.data_ptr(), S, dirs.data_ptr(), Dn,
+                      float(length), _ptr(T), float(vturb),
+                      None if lA is None else lA.ctypes.data,
+                      None if lnu is None else lnu.ctypes.data, float(gamma), float(av0),
+                      _ptr(out_rays), _ptr(out_av), _ptr(out_beta), _stream(dev))
+    res = {}
+    if out_av is not None:
+        res["av_eff"] = out_av
+    if out_beta is not None:
+        res["beta"] = out_beta.t()
+    if out_rays is not None:
+        res["rays"] = out_rays.permute(2, 1, 0)
+    return res
+
+
 class RayColumns(torch.autograd.Function):
     """(N, A) = RayColumns.apply(rho, tree, src, dirs, kappa), differentiable
     in rho through the library's adjoint walk."""

@@ -3,7 +3,8 @@
 This package builds the *inputs* of the column-density problem and nothing
 else: turbulent density fields, the leaf-only linear octree that stands for the
 contribution grid (paper Sec. 2.2 and Sec. 2.3.1), source points (the source
-grid of Sec. 2.2) and per-ray loss weights.  It holds none of the walk's
+grid of Sec. 2.2), per-ray loss weights, and the per-leaf line fields and
+per-source temperatures of the several-fields walk (Sec. 2.4).  It holds none of the walk's
 arithmetic (no leaf search, no slab test, no accumulation, no direction set):
 both the CPU oracle and the GPU library consume the arrays it returns.
 
@@ -26,6 +27,7 @@ from .octree import (
 )
 from .sources import cell_centres, leaf_centres, density_weighted_points, random_points
 from .configs import WORKLOADS, make_workload, Workload
+from .lines import LINES, line_inputs
 
 __all__ = [
     "gaussian_random_field",
@@ -48,4 +50,6 @@ __all__ = [
     "WORKLOADS",
     "make_workload",
     "Workload",
+    "LINES",
+    "line_inputs",
 ]

@@ -10,8 +10,9 @@ direction table, the FP32-Kahan forward walk (N and A = exp(-kappa N)), and
 the adjoint walk of L = sum w A (w ~ U(0,1) per ray) scattering dL/drho onto
 the leaves.  The value is ray-leaf steps per second of that pass: the leaf
 visits of the forward walk (the adjoint re-walks the same ones) divided by
-the time of the pass.  The FP64 walk over the same rays is timed after the
-pass and reported beside it.
+the time of the pass.  The FP64 walk over the same rays, and the
+several-fields walk (n_H and three lines: per-source escape probabilities
+and A_V,eff), are timed after the pass and reported beside it.
 
 Prints one JSON line.  --gpus N > 1 is refused: the library runs on one GPU.
 """
@@ -32,6 +33,9 @@ VALU_PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9  # CUs x SIMDs x lanes x clock
 CPU_SAMPLE_STRIDE = 4096
 BYTES_PER_STEP = {"k_forward_f32k": 13, "k_forward_f64": 17, "k_backward": 25}
 BYTES_PER_RAY = {"k_forward_f32k": 32, "k_forward_f64": 40, "k_backward": 32}
+# several-fields walk: n_H and three lines (key 8 + level 1 + 8 per field per step)
+SHIELD_LINES = 3
+SHIELD_BYTES_PER_STEP = 9 + 8 * (1 + SHIELD_LINES)
 
 
 def log(msg):
@@ -46,17 +50,18 @@ def parse():
     p.add_argument("--workload", type=int, default=4, help="workload index (0..4)")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-fp64", action="store_true")
+    p.add_argument("--no-shielding", action="store_true")
     p.add_argument("--copy-gb", type=float, default=4.0,
                    help="size of the device-to-device copy that measures achievable bandwidth")
     return p.parse_args()
 
 
-def kernel_source_hash():
-    """Hash of the sources that fix what the column kernels execute: the
-    device walk, the kernels with their launch shapes, and the octree's
-    search structures."""
+def kernel_source_hash(kernel_file="rt_walk.hip"):
+    """Hash of the sources that fix what a kernel executes: the device walk,
+    the kernel's own source with its launch shape, and the octree's search
+    structures."""
     h = hashlib.sha256()
-    for f in ("rt_ray.h", "rt_walk.hip", "rt_octree.cpp"):
+    for f in ("rt_ray.h", kernel_file, "rt_octree.cpp"):
         with open(os.path.join(ROOT, "paper_2605_09882_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -224,6 +229,42 @@ def main():
         del N64
         log(f"FP64 walk {ms64:.1f} ms")
 
+    # several fields per leaf (n_H and three lines) over the same rays:
+    # per-source escape probabilities and A_V,eff from one walk per ray
+    shield = None
+    if not args.no_shielding:
+        inp = W.line_inputs(w.tree, w.sources, SHIELD_LINES, 6000 + w.index)
+        F = torch.as_tensor(inp["fields"]).to(dev)
+        T = torch.as_tensor(inp["temp"]).to(dev)
+
+        def shield_call():
+            return rt.shielding(tree, F, src, dirs, inp["length"], temp=T, vturb=inp["vturb"],
+                                line_A=inp["line_A"], line_nu=inp["line_nu"])
+
+        shield_call()
+        torch.cuda.synchronize()
+        a, b = ev(), ev()
+        a.record()
+        for _ in range(args.steps):
+            res = shield_call()
+        b.record()
+        torch.cuda.synchronize()
+        ms_sh = a.elapsed_time(b) / args.steps
+        nf = 1 + SHIELD_LINES
+        bsh = total_steps * SHIELD_BYTES_PER_STEP + S * (24 + 8 + 8 * nf)
+        prof_sh = stored_counters("k_shielding", w.name, kernel_source_hash("rt_fields.hip"))
+        shield = {"fields": nf, "ms": round(ms_sh, 3), "steps_per_s": total_steps / (ms_sh / 1e3),
+                  "field_steps_per_s": nf * total_steps / (ms_sh / 1e3),
+                  "bytes_per_step": SHIELD_BYTES_PER_STEP,
+                  "algorithmic_gbs": round(bsh / (ms_sh / 1e3) / 1e9, 1),
+                  "vs_fp64_walk": round(ms_sh / fp64["ms"], 3) if fp64 else None,
+                  "av_eff_median": float(res["av_eff"].median()),
+                  "traffic": prof_sh["hbm_bytes_per_launch"] if prof_sh else None,
+                  "valu_frac": (round(prof_sh["valu_lane_ops_per_s"] / VALU_PEAK_LANE_OPS, 3)
+                                if prof_sh else None)}
+        del F, T, res
+        log(f"several-fields walk ({nf} fields) {ms_sh:.1f} ms")
+
     # roofline of the dominant kernel: algorithmic bytes per launch over its
     # measured duration.  Per ray-leaf step the method reads one leaf record
     # (Morton key 8 B, level 1 B, value 4 B FP32 / 8 B FP64); the adjoint
@@ -276,6 +317,7 @@ def main():
         "fp32k_forward_steps_per_s": total_steps / (fwd_ms / 1e3),
         "adjoint_steps_per_s": total_steps / (bwd_ms / 1e3),
         "fp64_walk": fp64,
+        "shielding": shield,
         "roofline": roofline,
         "cpu_baseline": cpu,
         "kernel_source_hash": src_hash,

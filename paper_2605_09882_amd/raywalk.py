@@ -195,8 +195,8 @@ def shielding(tree, fields, src, dirs, length, temp=None, vturb=0.0, line_A=(), 
     if K > 1:
         if temp is None:
             raise ValueError("lines need source temperatures")
-        T = torch.as_tensor(np.broadcast_to(np.asarray(temp, dtype=np.float64), (S,))
-                            if not torch.is_tensor(temp) else temp)
+        T = temp if torch.is_tensor(temp) else torch.as_tensor(
+            np.array(np.broadcast_to(np.asarray(temp, dtype=np.float64), (S,))))
         T = T.to(device=dev, dtype=torch.float64).contiguous()
         lA = np.ascontiguousarray(line_A, dtype=np.float64)
         lnu = np.ascontiguousarray(line_nu, dtype=np.float64)

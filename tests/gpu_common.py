@@ -6,6 +6,8 @@ import torch
 
 import workloads as W
 
+_EPS = np.finfo(np.float64).eps
+
 
 def require_gpu():
     if not torch.cuda.is_available():
@@ -86,6 +88,31 @@ def special_dirs():
     diag = np.array([[1, 1, 1], [-1, 1, -1], [1, -1, 0], [0, 1, 1], [3, -4, 12]], float)
     diag /= np.linalg.norm(diag, axis=1)[:, None]
     return np.vstack([axis, diag])
+
+
+def assert_shielding(got, ref, n_dirs, gamma=3.02, rays=True):
+    """rt_shielding outputs against the oracle's, to the bar derived in
+    test_gpu_shielding.py."""
+    bad = np.isnan(ref["av_eff"])
+    assert np.array_equal(np.isnan(got["av_eff"]), bad)
+    ok = ~bad
+    if rays:
+        g, r = got["rays"], ref["rays"]
+        assert g.shape == r.shape
+        assert np.all(np.isnan(g[bad])) and not np.isnan(g[ok]).any()
+        nh_g, nh_r = g[ok][..., 0], r[ok][..., 0]
+        diff = nh_g != nh_r
+        assert not diff.any(), f"N_H differs on {diff.sum()} rays: {nh_g[diff][:4]} vs {nh_r[diff][:4]}"
+        tg, tr = g[ok][..., 1:], r[ok][..., 1:]
+        assert np.all(np.abs(tg - tr) <= 4 * _EPS * np.abs(tr)), np.max(np.abs(tg - tr) / np.abs(tr))
+    a, b = got["av_eff"][ok], ref["av_eff"][ok]
+    tol = (2 * n_dirs + 4) * _EPS / abs(gamma) + 8 * _EPS * np.abs(b)
+    assert np.all(np.abs(a - b) <= tol), np.max(np.abs(a - b) - tol)
+    if ref["beta"].shape[1] > 0:
+        assert np.all(np.isnan(got["beta"][bad]))
+        a, b = got["beta"][ok], ref["beta"][ok]
+        assert np.all(np.abs(a - b) <= (2 * n_dirs + 8) * _EPS * np.abs(b)), \
+            np.max(np.abs(a - b) / np.abs(b))
 
 
 def random_dirs(count, seed):

@@ -9,7 +9,10 @@ finite non-negative columns, the uniform-density closed form N = t_exit on
 the workload's own topology); (iii) the adjoint is checked against the
 oracle's FP64 gradient on a source subsample, through the linearity
 identity sum_k rho_k dL/drho_k = sum_r g_r N_r on every ray, and against
-FP64 central differences on sampled leaves.
+FP64 central differences on sampled leaves; (iv) the several-fields walk
+(n_H and three lines) is compared with the oracle on a seeded source
+sample, and on every source A_V,eff lies between the smallest and the mean
+of its directions' extinctions from the FP64 column walk.
 """
 
 import numpy as np
@@ -17,11 +20,13 @@ import pytest
 import torch
 
 import workloads as W
-from gpu_common import require_gpu
+from gpu_common import assert_shielding, require_gpu
 
 pytestmark = pytest.mark.gpu
 
 N_SAMPLE_RAYS = 1500
+N_SAMPLE_SOURCES = 3000
+SHIELD_LINES = 3  # n_H and three lines: the configuration bench.py times
 
 
 @pytest.fixture(scope="module")
@@ -152,3 +157,41 @@ def test_fullsize_adjoint_merged512(rt, orc):
         _, Am = rt.columns(tree, rm, src, dirs_d, w.kappa)
         fd = float((wgt.double() * (Ap - Am)).sum() / (2 * hstep))
         assert abs(g_full[k] - fd) <= 1e-4 * abs(fd) + 1e-7 * np.abs(g_full).max(), (k, g_full[k], fd)
+
+
+@pytest.mark.parametrize("index", [4, 2])
+def test_fullsize_shielding(rt, orc, index):
+    w = _workload(index)
+    dev = torch.device("cuda")
+    dirs, _ = _dirs(rt, orc, w.nside)
+    tree = rt.Octree(w.tree.keys, w.tree.levels, w.tree.depth, dev)
+    src = torch.as_tensor(w.sources).to(dev)
+    dirs_d = torch.as_tensor(dirs).to(dev)
+    S, Dn = src.shape[0], dirs.shape[0]
+    inp = W.line_inputs(w.tree, w.sources, SHIELD_LINES, 6000 + index)
+    F = torch.as_tensor(inp["fields"]).to(dev)
+    T = torch.as_tensor(inp["temp"]).to(dev)
+    gamma, av0 = 3.02, 6.29e-22
+    out = rt.shielding(tree, F, src, dirs_d, inp["length"], temp=T, vturb=inp["vturb"],
+                       line_A=inp["line_A"], line_nu=inp["line_nu"], gamma=gamma, av0=av0)
+    av = out["av_eff"]
+    beta = out["beta"].cpu().numpy()
+    assert bool(torch.isfinite(av).all()) and bool((av >= 0).all())
+    assert np.isfinite(beta).all() and (beta > 0).all()
+    # every source: min_d av0 N_H <= A_V,eff <= mean_d av0 N_H (Jensen)
+    N, _ = rt.columns(tree, F[:, 0].contiguous(), src, dirs_d, with_A=False)
+    avd = av0 * (inp["length"] * N)
+    lo, hi = avd.min(dim=1).values, avd.mean(dim=1)
+    slack = 1e-12 * hi + (2 * Dn + 4) * 2.3e-16 / gamma
+    assert bool((av >= lo - slack).all()) and bool((av <= hi + slack).all())
+    del N, avd
+    # seeded sample against the oracle
+    rng = np.random.default_rng(7000 + index)
+    idx = np.sort(rng.choice(S, N_SAMPLE_SOURCES, replace=False))
+    ref = orc.shielding(w.tree, inp["fields"], w.sources[idx], dirs, length=inp["length"],
+                        temp=inp["temp"][idx], vturb=inp["vturb"], line_A=inp["line_A"],
+                        line_nu=inp["line_nu"], gamma=gamma, av0=av0, rays=False, threads=8)
+    assert ref["status"] == orc.OK
+    got = {"av_eff": av.cpu().numpy()[idx], "beta": beta[idx]}
+    assert_shielding(got, ref, Dn, gamma=gamma, rays=False)
+    torch.cuda.synchronize()

@@ -19,11 +19,10 @@ import pytest
 import torch
 
 import workloads as W
-from gpu_common import edge_sources, random_dirs, require_gpu, special_dirs
+from gpu_common import assert_shielding, edge_sources, random_dirs, require_gpu, special_dirs
 
 pytestmark = pytest.mark.gpu
 
-EPS = np.finfo(np.float64).eps
 GAMMA, AV0 = 3.02, 6.29e-22
 
 
@@ -49,29 +48,6 @@ def oracle_shielding(orc, tree, fields, src, dirs, inp, gamma=GAMMA, av0=AV0):
     return orc.shielding(tree, fields, src, dirs, length=inp["length"], temp=inp.get("temp"),
                          vturb=inp.get("vturb", 0.0), line_A=inp.get("line_A", ()),
                          line_nu=inp.get("line_nu", ()), gamma=gamma, av0=av0, threads=8)
-
-
-def assert_shielding(got, ref, n_dirs, gamma=GAMMA, rays=True):
-    bad = np.isnan(ref["av_eff"])
-    assert np.array_equal(np.isnan(got["av_eff"]), bad)
-    ok = ~bad
-    if rays:
-        g, r = got["rays"], ref["rays"]
-        assert g.shape == r.shape
-        assert np.all(np.isnan(g[bad])) and not np.isnan(g[ok]).any()
-        nh_g, nh_r = g[ok][..., 0], r[ok][..., 0]
-        diff = nh_g != nh_r
-        assert not diff.any(), f"N_H differs on {diff.sum()} rays: {nh_g[diff][:4]} vs {nh_r[diff][:4]}"
-        tg, tr = g[ok][..., 1:], r[ok][..., 1:]
-        assert np.all(np.abs(tg - tr) <= 4 * EPS * np.abs(tr)), np.max(np.abs(tg - tr) / np.abs(tr))
-    a, b = got["av_eff"][ok], ref["av_eff"][ok]
-    tol = (2 * n_dirs + 4) * EPS / abs(gamma) + 8 * EPS * np.abs(b)
-    assert np.all(np.abs(a - b) <= tol), np.max(np.abs(a - b) - tol)
-    if ref["beta"].shape[1] > 0:
-        assert np.all(np.isnan(got["beta"][bad]))
-        a, b = got["beta"][ok], ref["beta"][ok]
-        assert np.all(np.abs(a - b) <= (2 * n_dirs + 8) * EPS * np.abs(b)), \
-            np.max(np.abs(a - b) / np.abs(b))
 
 
 def _inputs(tree, src, n_lines, seed):

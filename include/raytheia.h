@@ -81,6 +81,16 @@ int64_t rt_healpix_npix(int nside);
  * Errors: RT_ERR_ARG (bad nside, null pointer). */
 int rt_healpix_dirs(int nside, double *dirs_out);
 
+/* The same centres in NESTED order (Gorski et al. 2005): pixel
+ * p = f nside^2 + i of base pixel f = 0..11, whose in-face index i
+ * interleaves the face coordinates (bit b of x -> bit 2b, of y -> bit 2b+1).
+ * The 4 pixels 4p .. 4p+3 at 2 nside subdivide pixel p at nside, which is
+ * what comparisons across resolutions need (sec. 3: a ray's reference
+ * column is the mean over the finer rays inside its pixel).  Each centre is
+ * bit-identical to the RING table's centre of the same pixel.  Errors:
+ * RT_ERR_ARG (bad nside, nside not a power of two, null pointer). */
+int rt_healpix_dirs_nested(int nside, double *dirs_out);
+
 /* ---------------------------------------------------------------------
  * Contribution grid: the leaf-only linear octree (sec. 2.3.1).
  * ------------------------------------------------------------------- */

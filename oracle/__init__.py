@@ -13,6 +13,8 @@ function).
 
 Functions and the passages they follow:
   healpix_ring   HEALPix RING pixel centres (the direction set of sec. 2.1).
+  healpix_nested the same centres in NESTED order (the sub-pixels of a pixel
+                 are consecutive: the reference means of sec. 3).
   check_tiling   leaf-only linear octree invariants (sec. 2.3.1).
   walk_one       one ray: DDA + Morton lookup + slab chord (sec. 2.3.1-2.3.2),
                  I = sum_k f_k r_k (sec. 2.3).
@@ -57,6 +59,8 @@ def _bind(lib):
     lib.orc_healpix_npix.argtypes = [ctypes.c_int]
     lib.orc_healpix_ring.restype = ctypes.c_int
     lib.orc_healpix_ring.argtypes = [ctypes.c_int, P]
+    lib.orc_healpix_nested.restype = ctypes.c_int
+    lib.orc_healpix_nested.argtypes = [ctypes.c_int, P]
     lib.orc_morton.restype = ctypes.c_uint64
     lib.orc_morton.argtypes = [i64, i64, i64, ctypes.c_int]
     lib.orc_check_tiling.restype = ctypes.c_int
@@ -108,6 +112,19 @@ def healpix_ring(nside, lib=None):
     st = lib.orc_healpix_ring(int(nside), _p(out))
     if st != OK:
         raise ValueError(f"orc_healpix_ring failed: {st}")
+    return out
+
+
+def healpix_nested(nside, lib=None):
+    """HEALPix NESTED pixel centres [12 nside^2, 3] (nside a power of two)."""
+    lib = lib or load()
+    n = healpix_npix(nside, lib)
+    if n < 0:
+        raise ValueError("nside must be >= 1")
+    out = np.empty((n, 3), dtype=np.float64)
+    st = lib.orc_healpix_nested(int(nside), _p(out))
+    if st != OK:
+        raise ValueError(f"orc_healpix_nested failed: {st}")
     return out
 
 

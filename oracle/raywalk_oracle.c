@@ -104,6 +104,58 @@ int orc_healpix_ring(int nside, double *dirs)
     return ORC_OK;
 }
 
+/* NESTED order (Gorski et al. 2005): pixel p = f nside^2 + i lies on base
+ * pixel f; the even bits of i give its x and the odd bits its y coordinate
+ * on the face.  The face's southmost corner is on ring face_row[f] nside at
+ * azimuth face_col[f] pi / 4; pixel (x, y) then lies on ring
+ * face_row nside - x - y - 1, at position (face_col n_r + x - y + 1 + s) / 2
+ * (1-based) in that ring, with n_r the ring's pixel count over 4 and s = 1
+ * for the belt rings whose centres sit on integer multiples of the azimuth
+ * step.  The centre is the RING table's centre of that (ring, position). */
+int orc_healpix_nested(int nside, double *dirs)
+{
+    static const int face_row[12] = {2, 2, 2, 2, 3, 3, 3, 3, 4, 4, 4, 4};
+    static const int face_col[12] = {1, 3, 5, 7, 0, 2, 4, 6, 1, 3, 5, 7};
+    int64_t npix = orc_healpix_npix(nside);
+    if (npix < 0 || !dirs || (nside & (nside - 1))) return ORC_ERR_ARG;
+    double *ring = (double *)malloc(sizeof(double) * 3 * npix);
+    if (!ring) return ORC_ERR_ARG;
+    orc_healpix_ring(nside, ring);
+    const int64_t N = nside;
+    for (int64_t p = 0; p < npix; ++p) {
+        int f = (int)(p / (N * N));
+        int64_t in_face = p % (N * N), x = 0, y = 0;
+        for (int b = 0; b < 32; ++b) {
+            x |= ((in_face >> (2 * b)) & 1) << b;
+            y |= ((in_face >> (2 * b + 1)) & 1) << b;
+        }
+        int64_t ring_i = face_row[f] * N - x - y - 1;  /* 1-based from the north */
+        int64_t nr, s, start;
+        if (ring_i < N) {                  /* north cap: 4 ring_i pixels */
+            nr = ring_i;
+            s = 0;
+            start = 2 * ring_i * (ring_i - 1);
+        } else if (ring_i <= 3 * N) {      /* belt: 4 N pixels */
+            nr = N;
+            s = (ring_i - N) % 2;
+            start = 2 * N * (N - 1) + (ring_i - N) * 4 * N;
+        } else {                           /* south cap */
+            nr = 4 * N - ring_i;
+            s = 0;
+            start = npix - 2 * nr * (nr + 1);
+        }
+        int64_t pos = (face_col[f] * nr + x - y + 1 + s) / 2;
+        if (pos > 4 * nr) pos -= 4 * nr;
+        if (pos < 1) pos += 4 * nr;
+        int64_t r = start + pos - 1;
+        dirs[3 * p + 0] = ring[3 * r + 0];
+        dirs[3 * p + 1] = ring[3 * r + 1];
+        dirs[3 * p + 2] = ring[3 * r + 2];
+    }
+    free(ring);
+    return ORC_OK;
+}
+
 /* ------------------------------------------------------------------ */
 /* Linear octree: Morton keys, tiling check, leaf lookup               */
 /* ------------------------------------------------------------------ */

@@ -11,7 +11,7 @@ passes torch device tensors and the current stream to it.
 
 from . import _abi
 from .raywalk import (Octree, RayColumns, columns, columns_backward, columns_trace, healpix_dirs,
-                      healpix_npix, ray_columns, shielding)
+                      healpix_dirs_nested, healpix_npix, ray_columns, shielding)
 
 __all__ = [
     "_abi",
@@ -21,6 +21,7 @@ __all__ = [
     "columns_backward",
     "columns_trace",
     "healpix_dirs",
+    "healpix_dirs_nested",
     "healpix_npix",
     "ray_columns",
     "shielding",

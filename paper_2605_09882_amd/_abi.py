@@ -30,6 +30,7 @@ EXPORTS = (
     "rt_last_error",
     "rt_healpix_npix",
     "rt_healpix_dirs",
+    "rt_healpix_dirs_nested",
     "rt_octree_workspace_bytes",
     "rt_build_octree",
     "rt_octree_free",
@@ -70,6 +71,7 @@ def load(path=None):
         "rt_last_error": (ctypes.c_char_p, []),
         "rt_healpix_npix": (I64, [I32]),
         "rt_healpix_dirs": (I32, [I32, P]),
+        "rt_healpix_dirs_nested": (I32, [I32, P]),
         "rt_octree_workspace_bytes": (ctypes.c_size_t, [I64, I32]),
         "rt_build_octree": (I32, [P, P, I64, I32, P, ctypes.c_size_t, V, ctypes.POINTER(V)]),
         "rt_octree_free": (None, [V]),
@@ -113,6 +115,10 @@ def rt_healpix_npix(nside):
 
 def rt_healpix_dirs(nside, dirs_out_ptr):
     _check(load().rt_healpix_dirs(int(nside), dirs_out_ptr), "rt_healpix_dirs")
+
+
+def rt_healpix_dirs_nested(nside, dirs_out_ptr):
+    _check(load().rt_healpix_dirs_nested(int(nside), dirs_out_ptr), "rt_healpix_dirs_nested")
 
 
 def rt_octree_workspace_bytes(n_leaves, max_depth):

@@ -117,40 +117,107 @@ int64_t cap_ring(int64_t p) {
 
 }  // namespace
 
+namespace {
+
+// Centre of pixel j (0-based, azimuth ascending) of ring i (1-based from the
+// north pole, 1 .. 4 nside - 1), as a unit vector: caps have 4 i' pixels
+// (i' the ring counted from the nearer pole) centred at z = +-(1 - i'^2 / (3
+// nside^2)), phi = (j + 1/2) pi / (2 i'); belt rings have 4 nside pixels at
+// z = 4/3 - 2 i / (3 nside), phi = (j + s) pi / (2 nside), s = 1/2 when
+// i + nside is even and 0 otherwise.
+void ring_pixel_centre(int64_t ns, int64_t i, int64_t j, double *out) {
+    const double pi = 3.14159265358979323846;
+    const double fns = (double)ns;
+    double z, phi;
+    if (i < ns) {  // north cap
+        z = 1.0 - (double)(i * i) / (3.0 * fns * fns);
+        phi = ((double)j + 0.5) * (pi / (2.0 * (double)i));
+    } else if (i <= 3 * ns) {  // belt
+        z = 4.0 / 3.0 - 2.0 * (double)i / (3.0 * fns);
+        const double shift = ((i + ns) & 1) ? 0.0 : 0.5;  // half-pixel offset
+        phi = ((double)j + shift) * (pi / (2.0 * fns));
+    } else {  // south cap, mirror of the north cap
+        const int64_t r = 4 * ns - i;
+        z = -(1.0 - (double)(r * r) / (3.0 * fns * fns));
+        phi = ((double)j + 0.5) * (pi / (2.0 * (double)r));
+    }
+    const double st = std::sqrt((1.0 - z) * (1.0 + z));
+    out[0] = st * std::cos(phi);
+    out[1] = st * std::sin(phi);
+    out[2] = z;
+}
+
+// Even (odd) bits of x packed together: the x (y) coordinate of a NESTED
+// in-face index.
+int64_t compact_bits(uint64_t x) {
+    x &= 0x5555555555555555ull;
+    x = (x | (x >> 1)) & 0x3333333333333333ull;
+    x = (x | (x >> 2)) & 0x0f0f0f0f0f0f0f0full;
+    x = (x | (x >> 4)) & 0x00ff00ff00ff00ffull;
+    x = (x | (x >> 8)) & 0x0000ffff0000ffffull;
+    x = (x | (x >> 16)) & 0x00000000ffffffffull;
+    return (int64_t)x;
+}
+
+}  // namespace
+
 int rt_healpix_dirs(int nside, double *dirs_out) {
     const int64_t npix = rt_healpix_npix(nside);
     if (npix < 0) return fail(RT_ERR_ARG, "nside %d out of range [1, 2^20]", nside);
     if (!dirs_out) return fail(RT_ERR_ARG, "null output pointer");
-    const double pi = 3.14159265358979323846;
     const int64_t ns = nside;
     const int64_t ncap = 2 * ns * (ns - 1);  // pixels in the north polar cap
-    const double fns = (double)ns;
     for (int64_t p = 0; p < npix; ++p) {
-        double z, phi;
+        int64_t i, j;
         if (p < ncap) {  // north cap: ring i has 4i pixels
-            const int64_t i = cap_ring(p);
-            const int64_t j = p - 2 * i * (i - 1);  // 0-based position
-            z = 1.0 - (double)(i * i) / (3.0 * fns * fns);
-            phi = ((double)j + 0.5) * (pi / (2.0 * (double)i));
+            i = cap_ring(p);
+            j = p - 2 * i * (i - 1);
         } else if (p < npix - ncap) {  // belt: 4 nside pixels per ring
             const int64_t q = p - ncap;
-            const int64_t i = q / (4 * ns) + ns;
-            const int64_t j = q % (4 * ns);
-            z = 4.0 / 3.0 - 2.0 * (double)i / (3.0 * fns);
-            const double shift = ((i + ns) & 1) ? 0.0 : 0.5;  // half-pixel offset
-            phi = ((double)j + shift) * (pi / (2.0 * fns));
-        } else {  // south cap, mirror of the north cap
+            i = q / (4 * ns) + ns;
+            j = q % (4 * ns);
+        } else {  // south cap, counted from the last pixel
             const int64_t q = npix - 1 - p;
-            const int64_t i = cap_ring(q);
-            const int64_t jm = q - 2 * i * (i - 1);      // position from the end
-            const int64_t j = 4 * i - 1 - jm;
-            z = -(1.0 - (double)(i * i) / (3.0 * fns * fns));
-            phi = ((double)j + 0.5) * (pi / (2.0 * (double)i));
+            const int64_t r = cap_ring(q);
+            i = 4 * ns - r;
+            j = 4 * r - 1 - (q - 2 * r * (r - 1));
         }
-        const double st = std::sqrt((1.0 - z) * (1.0 + z));
-        dirs_out[3 * p + 0] = st * std::cos(phi);
-        dirs_out[3 * p + 1] = st * std::sin(phi);
-        dirs_out[3 * p + 2] = z;
+        ring_pixel_centre(ns, i, j, dirs_out + 3 * p);
+    }
+    return ok();
+}
+
+int rt_healpix_dirs_nested(int nside, double *dirs_out) {
+    const int64_t npix = rt_healpix_npix(nside);
+    if (npix < 0) return fail(RT_ERR_ARG, "nside %d out of range [1, 2^20]", nside);
+    if (nside & (nside - 1)) return fail(RT_ERR_ARG, "NESTED needs nside a power of two, got %d", nside);
+    if (!dirs_out) return fail(RT_ERR_ARG, "null output pointer");
+    // base pixel f: its southmost corner lies on ring face_row[f] * nside,
+    // at azimuth face_col[f] * pi / 4 (Gorski et al. 2005, the 12 faces)
+    static const int face_row[12] = {2, 2, 2, 2, 3, 3, 3, 3, 4, 4, 4, 4};
+    static const int face_col[12] = {1, 3, 5, 7, 0, 2, 4, 6, 1, 3, 5, 7};
+    const int64_t ns = nside;
+    const int64_t per_face = ns * ns;
+    for (int64_t p = 0; p < npix; ++p) {
+        const int f = (int)(p / per_face);
+        const uint64_t in_face = (uint64_t)(p % per_face);
+        const int64_t ix = compact_bits(in_face), iy = compact_bits(in_face >> 1);
+        const int64_t i = face_row[f] * ns - ix - iy - 1;  // ring, 1-based from the north
+        int64_t nr, kshift;
+        if (i < ns) {
+            nr = i;
+            kshift = 0;
+        } else if (i > 3 * ns) {
+            nr = 4 * ns - i;
+            kshift = 0;
+        } else {
+            nr = ns;
+            kshift = (i - ns) & 1;
+        }
+        int64_t jp = (face_col[f] * nr + ix - iy + 1 + kshift) / 2;  // 1-based in the ring
+        if (jp > 4 * nr) jp -= 4 * nr;
+        if (jp < 1) jp += 4 * nr;
+        ring_pixel_centre(ns, i, jp - 1, dirs_out + 3 * p);
     }
     return ok();
 }

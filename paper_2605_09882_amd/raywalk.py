@@ -40,6 +40,17 @@ def healpix_dirs(nside):
     return out
 
 
+def healpix_dirs_nested(nside):
+    """HEALPix NESTED pixel centres as a host float64 array [12 nside^2, 3]
+    (nside a power of two); pixels 4p .. 4p+3 at 2 nside subdivide pixel p."""
+    n = _abi.rt_healpix_npix(nside)
+    if n < 0:
+        raise ValueError(f"nside {nside} out of range")
+    out = np.empty((n, 3), dtype=np.float64)
+    _abi.rt_healpix_dirs_nested(nside, out.ctypes.data)
+    return out
+
+
 class Octree:
     """A validated leaf-only linear octree staged on one GPU.
 

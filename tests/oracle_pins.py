@@ -7,6 +7,7 @@ copies of the oracle with a planted mistake and require that some pin fails.
 
 Which pin covers which oracle function:
   healpix_ring  pin_healpix_golden_nside1, pin_healpix_structure
+  healpix_nested pin_healpix_nested
   check_tiling  pin_tiling
   walk_one      pin_walk_golden, pin_uniform_closed_form, pin_chord_invariants,
                 pin_bruteforce, pin_amanatides_woo, pin_negation, pin_edge_cases,
@@ -83,6 +84,43 @@ def pin_healpix_structure(orc, lib):
 
 
 # ---------------------------------------------------------------- tiling
+
+def pin_healpix_nested(orc, lib):
+    """NESTED order: the same centres as RING (nside 1 in the same order),
+    and the hierarchy -- the 4 pixels 4p .. 4p+3 at 2 nside surround pixel
+    p: their mean direction lies within 0.2 pixel of p's centre and each of
+    them within 1.1 pixel (child pixel scale sqrt(4 pi / npix)); in-face
+    neighbours (indices differing in bit 0 or bit 1) are adjacent pixels; and
+    the face coordinates have the orientation of the definition."""
+    assert np.array_equal(orc.healpix_nested(1, lib=lib), orc.healpix_ring(1, lib=lib))
+    for ns in (2, 4, 8, 16):
+        ring = orc.healpix_ring(ns, lib=lib)
+        nest = orc.healpix_nested(ns, lib=lib)
+        assert np.array_equal(nest[np.lexsort(nest.T)], ring[np.lexsort(ring.T)]), ns
+        parent = orc.healpix_nested(ns // 2, lib=lib)
+        scale = np.sqrt(4 * np.pi / nest.shape[0])
+        kids = nest.reshape(-1, 4, 3)
+        mean = kids.mean(1)
+        mean /= np.linalg.norm(mean, axis=1)[:, None]
+        off = np.arccos(np.clip((mean * parent).sum(1), -1, 1)) / scale
+        assert off.max() < 0.2, (ns, off.max())
+        dist = np.arccos(np.clip((kids * parent[:, None, :]).sum(2), -1, 1)) / scale
+        assert dist.max() < 1.1, (ns, dist.max())
+        for bit in (1, 2):
+            q = np.arange(nest.shape[0]) ^ bit
+            step = np.arccos(np.clip((nest * nest[q]).sum(1), -1, 1)) / scale
+            assert step.max() < 1.6 and step.min() > 0.5, (ns, bit, step.min(), step.max())
+    # orientation: face coordinates start at the face's south corner, x runs
+    # toward its east corner and y toward its west corner, so of the 4 pixels
+    # of a face at nside 2, 4f is southmost, 4f+3 northmost, and 4f+1 lies
+    # east of 4f+2 on the same ring
+    d2 = orc.healpix_nested(2, lib=lib).reshape(12, 4, 3)
+    z = d2[:, :, 2]
+    assert np.all(z[:, 0] < z[:, 1]) and np.all(z[:, 1] == z[:, 2]) and np.all(z[:, 3] > z[:, 1])
+    phi = np.arctan2(d2[:, :, 1], d2[:, :, 0])
+    east = np.mod(phi[:, 1] - phi[:, 2], 2 * np.pi)
+    assert np.all((east > 0) & (east < np.pi)), east
+
 
 def pin_tiling(orc, lib):
     t = W.random_octree(4, 0.4, 11, min_level=1)
@@ -572,6 +610,7 @@ def pin_shielding_edge_cases(orc, lib):
 ALL_PINS = [
     pin_healpix_golden_nside1,
     pin_healpix_structure,
+    pin_healpix_nested,
     pin_tiling,
     pin_walk_golden,
     pin_uniform_closed_form,

@@ -57,11 +57,27 @@ def test_healpix_matches_oracle(orc, nside):
     assert np.abs(mine - ref).max() <= 1e-15
 
 
+@pytest.mark.parametrize("nside", [1, 2, 4, 8, 64])
+def test_healpix_nested_matches_oracle(orc, nside):
+    """The library's NESTED table against the oracle's, and row by row a
+    permutation of its own RING table (the same bits)."""
+    import paper_2605_09882_amd as rt
+    mine = rt.healpix_dirs_nested(nside)
+    ref = orc.healpix_nested(nside)
+    assert np.abs(mine - ref).max() <= 1e-15
+    ring = rt.healpix_dirs(nside)
+    assert np.array_equal(mine[np.lexsort(mine.T)], ring[np.lexsort(ring.T)])
+
+
 def test_healpix_errors(lib):
     out = np.empty((12, 3))
     assert lib.rt_healpix_dirs(0, out.ctypes.data) == _abi.RT_ERR_ARG
     assert b"nside" in lib.rt_last_error()
     assert lib.rt_healpix_dirs(1, None) == _abi.RT_ERR_ARG
+    assert lib.rt_healpix_dirs_nested(3, out.ctypes.data) == _abi.RT_ERR_ARG
+    assert b"power of two" in lib.rt_last_error()
+    assert lib.rt_healpix_dirs_nested(0, out.ctypes.data) == _abi.RT_ERR_ARG
+    assert lib.rt_healpix_dirs_nested(1, None) == _abi.RT_ERR_ARG
 
 
 def test_workspace_bytes(lib):

@@ -56,6 +56,14 @@ MUTANTS = {
     "beta_zero_depth_term": ("tau == 0.0 ? 1.0 :", "tau == 0.0 ? 0.0 :"),
     "av_eff_shift_lost": ("(xmin - log(sum / (double)Dn)) / gamma", "(-log(sum / (double)Dn)) / gamma"),
     "av_eff_mean_not_sum": ("log(sum / (double)Dn)", "log(sum)"),
+    "nested_x_y_swapped": ("x |= ((in_face >> (2 * b)) & 1) << b;", "x |= ((in_face >> (2 * b + 1)) & 1) << b;"),
+    "nested_face_row": ("static const int face_row[12] = {2, 2, 2, 2, 3, 3, 3, 3, 4, 4, 4, 4};",
+                        "static const int face_row[12] = {2, 2, 2, 2, 3, 3, 3, 3, 4, 4, 4, 3};"),
+    "nested_face_col": ("static const int face_col[12] = {1, 3, 5, 7, 0, 2, 4, 6, 1, 3, 5, 7};",
+                        "static const int face_col[12] = {1, 3, 5, 7, 0, 2, 4, 6, 1, 3, 7, 5};"),
+    "nested_belt_shift": ("s = (ring_i - N) % 2;", "s = (ring_i - N + 1) % 2;"),
+    "nested_diagonal_sign": ("int64_t pos = (face_col[f] * nr + x - y + 1 + s) / 2;",
+                             "int64_t pos = (face_col[f] * nr + y - x + 1 + s) / 2;"),
 }
 
 BATTERY = """

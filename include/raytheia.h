@@ -182,6 +182,27 @@ int rt_columns_trace(const rt_octree *tree, const double *d_src, int64_t n_src,
                      int64_t n_sample, int32_t *d_visited, int64_t cap, void *stream);
 
 /* ---------------------------------------------------------------------
+ * Angular-resolution comparison (sec. 3).
+ * ------------------------------------------------------------------- */
+
+/* Reference values and relative errors of a coarse direction set against a
+ * finer one, both in HEALPix NESTED order (rt_healpix_dirs_nested) with
+ * n_fine_dirs = 4^k n_coarse_dirs: the reference of coarse ray (q, s) is the
+ * mean of the fine rays q 4^k .. (q+1) 4^k - 1 of source s (the finer
+ * pixels inside pixel q), summed in that order and divided by 4^k, and its
+ * error is |coarse - reference| / reference (the relative column error of
+ * sec. 3; inf or NaN where the reference is 0).
+ *   d_fine    device f64 [n_fine_dirs][n_src] (rt_columns with stride_src = 1,
+ *             stride_dir = n_src);
+ *   d_coarse  device f64 [n_coarse_dirs][n_src], or NULL when d_err is NULL;
+ *   d_ref, d_err  device outputs or NULL, f64 [n_coarse_dirs][n_src].
+ * Errors: RT_ERR_ARG (null pointers, counts < 1, a ratio that is not a power
+ * of 4, overflow), RT_ERR_DEVICE. */
+int rt_nested_reference(const double *d_fine, int64_t n_fine_dirs, const double *d_coarse,
+                        int64_t n_coarse_dirs, int64_t n_src, double *d_ref, double *d_err,
+                        void *stream);
+
+/* ---------------------------------------------------------------------
  * Several fields per leaf: line optical depths, escape probabilities and
  * the effective visual extinction (sec. 2.4 and sec. 3).
  * ------------------------------------------------------------------- */

@@ -20,6 +20,9 @@ Functions and the passages they follow:
                  I = sum_k f_k r_k (sec. 2.3).
   columns        all (source, direction) rays, N and exp(-kappa N) (sec. 2.1).
   gradient       dL/drho_k = sum over rays of dL/dN * r_k (N is linear in rho).
+  nested_reference  reference columns of a coarse NESTED direction set: the
+                 mean of the finer rays inside each pixel, and the relative
+                 column error (sec. 3).
   shielding      several fields per leaf: per-ray N_H and line optical depths
                  tau (sec. 2.4), per-source escape probabilities beta
                  (sec. 2.4) and effective visual extinction A_V,eff (sec. 3).
@@ -73,6 +76,8 @@ def _bind(lib):
     lib.orc_gradient.restype = ctypes.c_int
     lib.orc_gradient.argtypes = [P, P, i64, ctypes.c_int, P, i64, P, i64, P, P]
     D = ctypes.c_double
+    lib.orc_nested_reference.restype = ctypes.c_int
+    lib.orc_nested_reference.argtypes = [P, i64, P, i64, i64, P, P]
     lib.orc_shielding.restype = ctypes.c_int
     lib.orc_shielding.argtypes = [P, P, i64, ctypes.c_int, P, ctypes.c_int, P, i64, P, i64, D, P,
                                   D, P, P, D, D, P, P, P]
@@ -267,3 +272,22 @@ def shielding(tree, fields, src, dirs, length=1.0, temp=None, vturb=0.0, line_A=
                                   zip(bounds[:-1], bounds[1:])))
     out["status"] = next((st for st in results if st != OK), OK)
     return out
+
+
+def nested_reference(fine, coarse=None, lib=None):
+    """fine [S, Dfine], coarse [S, Dcoarse] (Dfine = 4^k Dcoarse, NESTED
+    order): returns (ref, err) [S, Dcoarse] (err None without coarse)."""
+    lib = lib or load()
+    fine = _c(fine, np.float64)
+    S, Df = fine.shape
+    if coarse is not None:
+        coarse = _c(coarse, np.float64)
+        Dc = coarse.shape[1]
+    else:
+        raise ValueError("coarse columns are needed to fix the coarse direction count")
+    ref = np.empty((S, Dc))
+    err = np.empty((S, Dc))
+    st = lib.orc_nested_reference(_p(fine), Df, _p(coarse), Dc, S, _p(ref), _p(err))
+    if st != OK:
+        raise ValueError(f"orc_nested_reference failed: {st}")
+    return ref, err

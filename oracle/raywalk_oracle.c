@@ -528,3 +528,30 @@ int orc_shielding(const uint64_t *keys, const uint8_t *levels, int64_t n, int de
     free(vis); free(chords); free(zero); free(I); free(coef); free(bsum); free(x);
     return status;
 }
+
+/* ------------------------------------------------------------------ */
+/* Angular-resolution comparison                                       */
+/* ------------------------------------------------------------------ */
+
+/* Reference columns of a coarse HEALPix NESTED direction set from a finer
+ * one (sec. 3: the reference of a ray is the mean of the reference-resolution
+ * rays inside its pixel; with ratio = Dfine / Dcoarse = 4^k these are the
+ * fine rays q ratio .. (q+1) ratio - 1).  fine is [S][Dfine], coarse, ref and
+ * err are [S][Dcoarse]; ref = (sum in index order) / ratio and
+ * err = |coarse - ref| / ref.  coarse/err may be NULL together. */
+int orc_nested_reference(const double *fine, int64_t Dfine, const double *coarse, int64_t Dcoarse,
+                         int64_t S, double *ref, double *err)
+{
+    if (!fine || Dcoarse < 1 || S < 0 || Dfine % Dcoarse != 0) return ORC_ERR_ARG;
+    const int64_t ratio = Dfine / Dcoarse;
+    for (int64_t s = 0; s < S; ++s) {
+        for (int64_t q = 0; q < Dcoarse; ++q) {
+            double sum = 0.0;
+            for (int64_t k = 0; k < ratio; ++k) sum = sum + fine[s * Dfine + q * ratio + k];
+            const double r = sum / (double)ratio;
+            if (ref) ref[s * Dcoarse + q] = r;
+            if (err && coarse) err[s * Dcoarse + q] = fabs(coarse[s * Dcoarse + q] - r) / r;
+        }
+    }
+    return ORC_OK;
+}

@@ -40,6 +40,7 @@ EXPORTS = (
     "rt_columns_backward",
     "rt_columns_trace",
     "rt_shielding",
+    "rt_nested_reference",
 )
 
 RT_MAX_FIELDS = 8
@@ -81,6 +82,7 @@ def load(path=None):
         "rt_columns_backward": (I32, [V, P, I64, P, I64, D, P, P, P, I64, I64, P, V]),
         "rt_columns_trace": (I32, [V, P, I64, P, I64, P, P, I64, I64, P, I64, P, I64, V]),
         "rt_shielding": (I32, [V, P, I32, P, I64, P, I64, D, P, D, P, P, D, D, P, P, P, V]),
+        "rt_nested_reference": (I32, [P, I64, P, I64, I64, P, P, V]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -176,3 +178,9 @@ def rt_shielding(handle, fields_ptr, n_fields, src_ptr, n_src, dirs_ptr, n_dirs,
                                int(n_dirs), float(length), temp_ptr, float(vturb), line_A_ptr,
                                line_nu_ptr, float(gamma), float(av0), rays_ptr, av_eff_ptr,
                                beta_ptr, stream), "rt_shielding")
+
+
+def rt_nested_reference(fine_ptr, n_fine_dirs, coarse_ptr, n_coarse_dirs, n_src, ref_ptr, err_ptr,
+                        stream):
+    _check(load().rt_nested_reference(fine_ptr, int(n_fine_dirs), coarse_ptr, int(n_coarse_dirs),
+                                      int(n_src), ref_ptr, err_ptr, stream), "rt_nested_reference")

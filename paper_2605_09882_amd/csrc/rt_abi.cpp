@@ -273,6 +273,28 @@ int rt_columns_trace(const rt_octree *tree, const double *d_src, int64_t n_src,
 }
 
 // ---------------------------------------------------------------------
+// Angular-resolution comparison
+// ---------------------------------------------------------------------
+
+int rt_nested_reference(const double *d_fine, int64_t n_fine_dirs, const double *d_coarse,
+                        int64_t n_coarse_dirs, int64_t n_src, double *d_ref, double *d_err,
+                        void *stream) {
+    if (!d_fine) return fail(RT_ERR_ARG, "null fine columns");
+    if (n_coarse_dirs < 1 || n_src < 1 || n_fine_dirs < n_coarse_dirs)
+        return fail(RT_ERR_ARG, "need n_src >= 1 and n_fine_dirs >= n_coarse_dirs >= 1");
+    if (n_fine_dirs > INT64_MAX / n_src) return fail(RT_ERR_ARG, "n_fine_dirs * n_src overflows");
+    if (n_fine_dirs % n_coarse_dirs != 0) return fail(RT_ERR_ARG, "n_fine_dirs not a multiple of n_coarse_dirs");
+    const int64_t ratio = n_fine_dirs / n_coarse_dirs;
+    if (ratio & (ratio - 1) || (__builtin_ctzll((unsigned long long)ratio) & 1))
+        return fail(RT_ERR_ARG, "n_fine_dirs / n_coarse_dirs = %lld is not a power of 4", (long long)ratio);
+    if (d_err && !d_coarse) return fail(RT_ERR_ARG, "relative errors need the coarse columns");
+    if (!d_ref && !d_err) return ok();
+    hipError_t e = rt::launch_nested_reference(d_fine, d_coarse, n_coarse_dirs, n_src, ratio, d_ref,
+                                               d_err, static_cast<hipStream_t>(stream));
+    return device_status(e, "nested reference launch");
+}
+
+// ---------------------------------------------------------------------
 // Several fields per leaf
 // ---------------------------------------------------------------------
 

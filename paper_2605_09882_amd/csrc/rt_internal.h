@@ -84,6 +84,10 @@ hipError_t launch_shielding(const TreeView &tree, const RayBatch &rays, const do
                             int n_fields, const ShieldingParams &p, double *ray_out,
                             double *av_eff, double *beta, hipStream_t stream);
 
+hipError_t launch_nested_reference(const double *fine, const double *coarse, int64_t n_coarse,
+                                   int64_t n_src, int64_t ratio, double *ref, double *err,
+                                   hipStream_t stream);
+
 hipError_t launch_trace(const TreeView &tree, const RayBatch &rays, int32_t *steps,
                         uint64_t *hash, const int64_t *sample, int64_t n_sample,
                         int32_t *visited, int64_t cap, hipStream_t stream);

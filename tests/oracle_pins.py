@@ -14,6 +14,7 @@ Which pin covers which oracle function:
                 pin_deep_tree, pin_kahan_compensation
   columns       pin_linearity_and_refinement, pin_columns_consistency, pin_kahan_bound
   gradient      pin_gradient
+  nested_reference pin_nested_reference
   shielding     pin_shielding_integrals, pin_line_depth_constants,
                 pin_escape_probability, pin_av_eff, pin_shielding_edge_cases
 """
@@ -464,6 +465,27 @@ def pin_gradient(orc, lib):
         assert abs(fd - grad[k]) <= 1e-8 * scale
 
 
+def pin_nested_reference(orc, lib):
+    """Reference of a coarse NESTED pixel = mean of its 4^k finer pixels:
+    with the fine values equal to their own index the mean of pixel q is
+    q 4^k + (4^k - 1) / 2 exactly; two stages of coarsening equal one; the
+    error is 0 for coarse = reference and 1 for coarse = 2 reference."""
+    S = 3
+    for dc, k in ((12, 1), (12, 2), (48, 1), (12, 3)):
+        r = 4 ** k
+        fine = np.tile(np.arange(dc * r, dtype=np.float64), (S, 1)) + np.arange(S)[:, None] * 1e6
+        want = np.arange(dc) * r + (r - 1) / 2.0 + np.arange(S)[:, None] * 1e6
+        ref, err = orc.nested_reference(fine, want, lib=lib)
+        assert np.array_equal(ref, want) and np.all(err == 0.0)
+        _, err2 = orc.nested_reference(fine, 2 * want[:, :], lib=lib)
+        pos = want > 0
+        assert np.all(err2[pos] == 1.0)
+        if k >= 2:
+            mid, _ = orc.nested_reference(fine, np.zeros((S, dc * r // 4)), lib=lib)
+            two, _ = orc.nested_reference(mid, want, lib=lib)
+            assert np.array_equal(two, ref)
+
+
 # ---------------------------------------------------------------- several fields per leaf
 
 AXES = np.array([[1, 0, 0], [-1, 0, 0], [0, 1, 0], [0, -1, 0], [0, 0, 1], [0, 0, -1]], float)
@@ -625,6 +647,7 @@ ALL_PINS = [
     pin_kahan_compensation,
     pin_kahan_bound,
     pin_gradient,
+    pin_nested_reference,
     pin_shielding_integrals,
     pin_line_depth_constants,
     pin_escape_probability,

@@ -62,6 +62,9 @@ MUTANTS = {
     "nested_face_col": ("static const int face_col[12] = {1, 3, 5, 7, 0, 2, 4, 6, 1, 3, 5, 7};",
                         "static const int face_col[12] = {1, 3, 5, 7, 0, 2, 4, 6, 1, 3, 7, 5};"),
     "nested_belt_shift": ("s = (ring_i - N) % 2;", "s = (ring_i - N + 1) % 2;"),
+    "nested_reference_strided": ("sum = sum + fine[s * Dfine + q * ratio + k];",
+                                 "sum = sum + fine[s * Dfine + q + k * Dcoarse];"),
+    "nested_reference_sum": ("const double r = sum / (double)ratio;", "const double r = sum;"),
     "nested_diagonal_sign": ("int64_t pos = (face_col[f] * nr + x - y + 1 + s) / 2;",
                              "int64_t pos = (face_col[f] * nr + y - x + 1 + s) / 2;"),
 }

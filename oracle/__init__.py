@@ -20,6 +20,8 @@ Functions and the passages they follow:
                  I = sum_k f_k r_k (sec. 2.3).
   columns        all (source, direction) rays, N and exp(-kappa N) (sec. 2.1).
   gradient       dL/drho_k = sum over rays of dL/dN * r_k (N is linear in rho).
+  grid_tree      the contribution grid from a uniform grid by the density +
+                 uniformity rule (sec. 2.4): keys, levels, mean values.
   nested_reference  reference columns of a coarse NESTED direction set: the
                  mean of the finer rays inside each pixel, and the relative
                  column error (sec. 3).
@@ -76,6 +78,8 @@ def _bind(lib):
     lib.orc_gradient.restype = ctypes.c_int
     lib.orc_gradient.argtypes = [P, P, i64, ctypes.c_int, P, i64, P, i64, P, P]
     D = ctypes.c_double
+    lib.orc_grid_tree.restype = ctypes.c_int
+    lib.orc_grid_tree.argtypes = [P, ctypes.c_int, D, D, P, P, P, P]
     lib.orc_nested_reference.restype = ctypes.c_int
     lib.orc_nested_reference.argtypes = [P, i64, P, i64, i64, P, P]
     lib.orc_shielding.restype = ctypes.c_int
@@ -291,3 +295,21 @@ def nested_reference(fine, coarse=None, lib=None):
     if st != OK:
         raise ValueError(f"orc_nested_reference failed: {st}")
     return ref, err
+
+
+def grid_tree(grid_morton, depth, density_floor, rel_uniformity=0.01, lib=None):
+    """Leaf keys (uint64), levels (uint8) and mean values (float64) of the
+    refinement rule applied to a Morton-ordered [8^depth] grid."""
+    lib = lib or load()
+    g = _c(grid_morton, np.float64).reshape(-1)
+    assert g.shape[0] == 8 ** depth
+    keys = np.empty(g.shape[0], dtype=np.uint64)
+    levels = np.empty(g.shape[0], dtype=np.uint8)
+    values = np.empty(g.shape[0])
+    n = ctypes.c_int64()
+    st = lib.orc_grid_tree(_p(g), int(depth), float(density_floor), float(rel_uniformity), _p(keys),
+                           _p(levels), _p(values), ctypes.byref(n))
+    if st != OK:
+        raise ValueError(f"orc_grid_tree failed: {st}")
+    k = n.value
+    return keys[:k].copy(), levels[:k].copy(), values[:k].copy()

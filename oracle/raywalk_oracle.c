@@ -555,3 +555,84 @@ int orc_nested_reference(const double *fine, int64_t Dfine, const double *coarse
     }
     return ORC_OK;
 }
+
+/* ------------------------------------------------------------------ */
+/* Contribution grid from a uniform grid                               */
+/* ------------------------------------------------------------------ */
+
+/* The leaf-only octree of the paper's refinement rule (sec. 2.4, the AMR
+ * contribution grid): starting from the root, a cell of level L < D is
+ * split into its 8 children iff its largest fine value reaches floor and
+ * its relative variation (max - min) / max reaches rel, evaluated as
+ * max >= floor && (max - min) >= rel * max over the fine cells it covers;
+ * an unsplit cell, or a cell at level D, is a leaf.  A leaf's value is the
+ * mean of its fine cells, defined level by level as the mean of its 8
+ * children's values (summed in child order, divided by 8).
+ * grid is [8^D] in Morton order (fine cell i has key i).  Outputs, in
+ * Morton order: keys, levels, values (capacity 8^D each); *n = leaf count. */
+
+static int64_t tree_cells_before(int L) { return (((int64_t)1 << (3 * L)) - 1) / 7; }
+
+static void emit_leaves(int L, int64_t c, int D, const double *mx, const double *mn,
+                        const double *mean, const double *grid, double floor_, double rel,
+                        uint64_t *keys, uint8_t *levels, double *values, int64_t *n)
+{
+    int split = 0;
+    if (L < D) {
+        const int64_t at = tree_cells_before(L) + c;
+        split = mx[at] >= floor_ && (mx[at] - mn[at]) >= rel * mx[at];
+    }
+    if (!split) {
+        keys[*n] = (uint64_t)c << (3 * (D - L));
+        levels[*n] = (uint8_t)L;
+        values[*n] = L < D ? mean[tree_cells_before(L) + c] : grid[c];
+        *n += 1;
+        return;
+    }
+    for (int j = 0; j < 8; ++j)
+        emit_leaves(L + 1, 8 * c + j, D, mx, mn, mean, grid, floor_, rel, keys, levels, values, n);
+}
+
+int orc_grid_tree(const double *grid, int D, double floor_, double rel, uint64_t *keys,
+                  uint8_t *levels, double *values, int64_t *n)
+{
+    if (!grid || D < 0 || D > 10 || !keys || !levels || !values || !n) return ORC_ERR_ARG;
+    const int64_t cells = tree_cells_before(D);  /* all cells of levels 0 .. D-1 */
+    double *mx = (double *)malloc(sizeof(double) * (cells > 0 ? cells : 1));
+    double *mn = (double *)malloc(sizeof(double) * (cells > 0 ? cells : 1));
+    double *mean = (double *)malloc(sizeof(double) * (cells > 0 ? cells : 1));
+    if (!mx || !mn || !mean) {
+        free(mx); free(mn); free(mean);
+        return ORC_ERR_ARG;
+    }
+    /* max, min and mean of every cell, from level D-1 up to the root */
+    for (int L = D - 1; L >= 0; --L) {
+        const int64_t count = (int64_t)1 << (3 * L);
+        for (int64_t c = 0; c < count; ++c) {
+            double hi = -INFINITY, lo = INFINITY, sum = 0.0;
+            for (int j = 0; j < 8; ++j) {
+                const int64_t child = 8 * c + j;
+                double chi, clo, cmean;
+                if (L + 1 == D) {
+                    chi = clo = cmean = grid[child];
+                } else {
+                    const int64_t at = tree_cells_before(L + 1) + child;
+                    chi = mx[at];
+                    clo = mn[at];
+                    cmean = mean[at];
+                }
+                if (chi > hi) hi = chi;
+                if (clo < lo) lo = clo;
+                sum = sum + cmean;
+            }
+            const int64_t at = tree_cells_before(L) + c;
+            mx[at] = hi;
+            mn[at] = lo;
+            mean[at] = sum / 8.0;
+        }
+    }
+    *n = 0;
+    emit_leaves(0, 0, D, mx, mn, mean, grid, floor_, rel, keys, levels, values, n);
+    free(mx); free(mn); free(mean);
+    return ORC_OK;
+}

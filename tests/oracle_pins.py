@@ -15,6 +15,7 @@ Which pin covers which oracle function:
   columns       pin_linearity_and_refinement, pin_columns_consistency, pin_kahan_bound
   gradient      pin_gradient
   nested_reference pin_nested_reference
+  grid_tree     pin_grid_tree_closed_forms, pin_grid_tree_rule
   shielding     pin_shielding_integrals, pin_line_depth_constants,
                 pin_escape_probability, pin_av_eff, pin_shielding_edge_cases
 """
@@ -486,6 +487,70 @@ def pin_nested_reference(orc, lib):
             assert np.array_equal(two, ref)
 
 
+def pin_grid_tree_closed_forms(orc, lib):
+    """A uniform grid, or one below the floor, is one leaf (the root) with
+    the grid's value; one hot cell in a uniform background above the floor
+    splits exactly its D ancestors, giving 1 + 7 D leaves with the hot cell
+    alone at level D; the split tests are inclusive (max == floor splits,
+    (max - min) == rel max splits)."""
+    D = 3
+    n = 8 ** D
+    k, lv, v = orc.grid_tree(np.full(n, 2.5), D, 1.0, 0.01, lib=lib)
+    assert list(k) == [0] and list(lv) == [0] and v[0] == 2.5
+    rng = np.random.default_rng(91)
+    k, lv, v = orc.grid_tree(rng.random(n) * 0.5, D, 1.0, 0.01, lib=lib)
+    assert list(k) == [0] and list(lv) == [0]
+    hot = 300
+    g = np.full(n, 4.0)
+    g[hot] = 8.0
+    k, lv, v = orc.grid_tree(g, D, 1.0, 0.01, lib=lib)
+    assert len(k) == 1 + 7 * D
+    assert orc.check_tiling(k, lv, D, lib=lib) == orc.OK
+    assert np.sum(lv == D) == 8 and k[lv == D].min() <= hot <= k[lv == D].max()
+    assert v[list(k).index(hot)] == 8.0
+    # the mean of a leaf covering the hot cell's siblings and itself
+    parent = hot & ~7
+    assert np.sum((k >= parent) & (k < parent + 8)) == 8
+    # inclusive tests: two values 1.0 and 0.75 in one level-2 cell
+    g = np.full(n, 1.0)
+    g[:8] = 0.75
+    for rel, floor, want_split in ((0.25, 1.0, True), (0.2500001, 1.0, False), (0.25, 1.0000001, False)):
+        k, lv, v = orc.grid_tree(g, D, floor, rel, lib=lib)
+        assert (len(k) > 1) == want_split, (rel, floor, len(k))
+
+
+def pin_grid_tree_rule(orc, lib):
+    """On lognormal clouds: the leaves tile the box; every leaf fails the
+    rule (or is at level D) and every leaf's parent passes it, with max and
+    min taken directly over the covered fine cells; each value is the mean
+    of the covered fine cells (to 1e-14); keys and levels equal those of the
+    numpy generator of the workloads, an independent implementation."""
+    for n, seed, q in ((16, 92, 60.0), (32, 93, 75.0)):
+        D = int(np.log2(n))
+        rho = W.lognormal(W.gaussian_random_field(n, -4.0, seed), 2.0)
+        grid = W.octree.grid_to_morton(rho)
+        floor = float(np.percentile(rho, q))
+        k, lv, v = orc.grid_tree(grid, D, floor, 0.01, lib=lib)
+        assert orc.check_tiling(k, lv, D, lib=lib) == orc.OK
+        ref = W.uniformity_merged_octree(rho, floor, 0.01)
+        assert np.array_equal(k, ref.keys) and np.array_equal(lv, ref.levels)
+
+        def rule(key, level):
+            span = 8 ** (D - int(level))
+            block = grid[int(key): int(key) + span]
+            mx, mn = block.max(), block.min()
+            return mx >= floor and (mx - mn) >= 0.01 * mx
+
+        for key, level, val in zip(k, lv, v):
+            span = 8 ** (D - int(level))
+            block = grid[int(key): int(key) + span]
+            assert abs(val - block.mean()) <= 1e-14 * abs(block.mean())
+            assert int(level) == D or not rule(key, level)
+            if int(level) > 0:
+                pspan = 8 ** (D - int(level) + 1)
+                assert rule(int(key) // pspan * pspan, int(level) - 1)
+
+
 # ---------------------------------------------------------------- several fields per leaf
 
 AXES = np.array([[1, 0, 0], [-1, 0, 0], [0, 1, 0], [0, -1, 0], [0, 0, 1], [0, 0, -1]], float)
@@ -648,6 +713,8 @@ ALL_PINS = [
     pin_kahan_bound,
     pin_gradient,
     pin_nested_reference,
+    pin_grid_tree_closed_forms,
+    pin_grid_tree_rule,
     pin_shielding_integrals,
     pin_line_depth_constants,
     pin_escape_probability,

@@ -65,6 +65,13 @@ MUTANTS = {
     "nested_reference_strided": ("sum = sum + fine[s * Dfine + q * ratio + k];",
                                  "sum = sum + fine[s * Dfine + q + k * Dcoarse];"),
     "nested_reference_sum": ("const double r = sum / (double)ratio;", "const double r = sum;"),
+    "grid_floor_exclusive": ("split = mx[at] >= floor_ && (mx[at] - mn[at]) >= rel * mx[at];",
+                             "split = mx[at] > floor_ && (mx[at] - mn[at]) >= rel * mx[at];"),
+    "grid_variation_over_min": ("split = mx[at] >= floor_ && (mx[at] - mn[at]) >= rel * mx[at];",
+                                "split = mx[at] >= floor_ && (mx[at] - mn[at]) >= rel * mn[at];"),
+    "grid_mean_not_divided": ("mean[at] = sum / 8.0;", "mean[at] = sum;"),
+    "grid_children_reversed": ("emit_leaves(L + 1, 8 * c + j, D,", "emit_leaves(L + 1, 8 * c + 7 - j, D,"),
+    "grid_key_coarse_shift": ("keys[*n] = (uint64_t)c << (3 * (D - L));", "keys[*n] = (uint64_t)c << (3 * (D - L - 1));"),
     "nested_diagonal_sign": ("int64_t pos = (face_col[f] * nr + x - y + 1 + s) / 2;",
                              "int64_t pos = (face_col[f] * nr + y - x + 1 + s) / 2;"),
 }

@@ -12,7 +12,8 @@ the leaves.  The value is ray-leaf steps per second of that pass: the leaf
 visits of the forward walk (the adjoint re-walks the same ones) divided by
 the time of the pass.  The FP64 walk over the same rays, and the
 several-fields walk (n_H and three lines: per-source escape probabilities
-and A_V,eff), are timed after the pass and reported beside it.
+and A_V,eff), and the construction of the contribution grid from the 512^3
+grid on the device, are timed after the pass and reported beside it.
 
 Prints one JSON line.  --gpus N > 1 is refused: the library runs on one GPU.
 """
@@ -51,6 +52,7 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-fp64", action="store_true")
     p.add_argument("--no-shielding", action="store_true")
+    p.add_argument("--no-grid-tree", action="store_true")
     p.add_argument("--copy-gb", type=float, default=4.0,
                    help="size of the device-to-device copy that measures achievable bandwidth")
     return p.parse_args()
@@ -265,6 +267,34 @@ def main():
         del F, T, res
         log(f"several-fields walk ({nf} fields) {ms_sh:.1f} ms")
 
+    # the contribution grid rebuilt on the device from the workload's 512^3
+    # grid (the same field and rule as the host generator)
+    build = None
+    if not args.no_grid_tree and "density_floor" in w.info:
+        n_side = 1 << w.tree.depth
+        field = W.lognormal(W.gaussian_random_field(n_side, -4.0, 1000 + w.index), 2.0)
+        grid = torch.as_tensor(W.octree.grid_to_morton(field)).to(dev)
+        del field
+        floor = w.info["density_floor"]
+        keys, _, _ = rt.grid_tree(grid, w.tree.depth, floor)
+        same = bool(torch.equal(keys, torch.as_tensor(w.tree.keys.view(np.int64)).to(dev)))
+        del keys
+        times = []
+        for _ in range(max(args.steps, 3)):
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            keys, _, _ = rt.grid_tree(grid, w.tree.depth, floor)
+            times.append(time.perf_counter() - t1)
+            del keys
+        ms_b = 1e3 * min(times)
+        cells = grid.numel()
+        build = {"cells": cells, "leaves": w.tree.n, "ms": round(ms_b, 3),
+                 "cells_per_s": cells / (ms_b / 1e3), "same_tree_as_host": same,
+                 "timing": "wall clock per call, including the leaf-count read-back"}
+        del grid
+        log(f"grid tree on the device: {cells} cells -> {w.tree.n} leaves in {ms_b:.2f} ms "
+            f"(same as the host tree: {same})")
+
     # roofline of the dominant kernel: algorithmic bytes per launch over its
     # measured duration.  Per ray-leaf step the method reads one leaf record
     # (Morton key 8 B, level 1 B, value 4 B FP32 / 8 B FP64); the adjoint
@@ -318,6 +348,7 @@ def main():
         "adjoint_steps_per_s": total_steps / (bwd_ms / 1e3),
         "fp64_walk": fp64,
         "shielding": shield,
+        "grid_tree": build,
         "roofline": roofline,
         "cpu_baseline": cpu,
         "kernel_source_hash": src_hash,

@@ -128,6 +128,35 @@ void rt_octree_free(rt_octree *tree);
 int64_t rt_octree_leaves(const rt_octree *tree);
 int rt_octree_depth(const rt_octree *tree);
 
+/* Device bytes of the workspace of rt_grid_tree at depth 1..10; 0 otherwise. */
+size_t rt_grid_tree_workspace_bytes(int depth);
+
+/* Builds the contribution grid on the device from a uniform grid by the
+ * density + uniformity rule (sec. 2.4): starting from the root, a cell of
+ * level L < depth is split into its 8 children iff, over the fine cells it
+ * covers, max >= density_floor and (max - min) >= rel_uniformity * max; an
+ * unsplit cell whose ancestors are all split, or a fine cell under a split
+ * level-(depth-1) cell, is a leaf.  A leaf's value is the mean of its fine
+ * cells, formed level by level as the mean of its 8 children's values
+ * (summed in child order, divided by 8).
+ *   d_grid      device f64 [8^depth], finite values in Morton order (fine cell
+ *               i has Morton key i at this depth);
+ *   depth       1..10;
+ *   d_workspace device, >= rt_grid_tree_workspace_bytes(depth) bytes,
+ *               256-byte aligned (the max/min/mean/split pyramid and the
+ *               block offsets);
+ *   d_keys, d_levels, d_values  device outputs with room for 8^depth
+ *               entries: the leaves' Morton keys at this depth, levels and
+ *               values, in key order (the input of rt_build_octree and of
+ *               the walks);
+ *   d_n_leaves  device int64 output, the leaf count.
+ * Device work is queued on stream; nothing is read back.  Errors:
+ * RT_ERR_ARG (depth, null pointers, non-finite parameters),
+ * RT_ERR_WORKSPACE, RT_ERR_DEVICE. */
+int rt_grid_tree(const double *d_grid, int depth, double density_floor, double rel_uniformity,
+                 void *d_workspace, size_t workspace_bytes, uint64_t *d_keys, uint8_t *d_levels,
+                 double *d_values, int64_t *d_n_leaves, void *stream);
+
 /* ---------------------------------------------------------------------
  * Column densities (sec. 2.3: I(p,q) = sum_k f_k r_k with f = rho).
  * ------------------------------------------------------------------- */

@@ -10,8 +10,8 @@ passes torch device tensors and the current stream to it.
 """
 
 from . import _abi
-from .raywalk import (Octree, RayColumns, columns, columns_backward, columns_trace, healpix_dirs,
-                      healpix_dirs_nested, healpix_npix, ray_columns, shielding)
+from .raywalk import (Octree, RayColumns, columns, columns_backward, columns_trace, grid_tree,
+                      healpix_dirs, healpix_dirs_nested, healpix_npix, ray_columns, shielding)
 
 __all__ = [
     "_abi",
@@ -20,6 +20,7 @@ __all__ = [
     "columns",
     "columns_backward",
     "columns_trace",
+    "grid_tree",
     "healpix_dirs",
     "healpix_dirs_nested",
     "healpix_npix",

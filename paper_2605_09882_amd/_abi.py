@@ -41,6 +41,8 @@ EXPORTS = (
     "rt_columns_trace",
     "rt_shielding",
     "rt_nested_reference",
+    "rt_grid_tree_workspace_bytes",
+    "rt_grid_tree",
 )
 
 RT_MAX_FIELDS = 8
@@ -83,6 +85,8 @@ def load(path=None):
         "rt_columns_trace": (I32, [V, P, I64, P, I64, P, P, I64, I64, P, I64, P, I64, V]),
         "rt_shielding": (I32, [V, P, I32, P, I64, P, I64, D, P, D, P, P, D, D, P, P, P, V]),
         "rt_nested_reference": (I32, [P, I64, P, I64, I64, P, P, V]),
+        "rt_grid_tree_workspace_bytes": (ctypes.c_size_t, [I32]),
+        "rt_grid_tree": (I32, [P, I32, D, D, P, ctypes.c_size_t, P, P, P, P, V]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -184,3 +188,14 @@ def rt_nested_reference(fine_ptr, n_fine_dirs, coarse_ptr, n_coarse_dirs, n_src,
                         stream):
     _check(load().rt_nested_reference(fine_ptr, int(n_fine_dirs), coarse_ptr, int(n_coarse_dirs),
                                       int(n_src), ref_ptr, err_ptr, stream), "rt_nested_reference")
+
+
+def rt_grid_tree_workspace_bytes(depth):
+    return int(load().rt_grid_tree_workspace_bytes(int(depth)))
+
+
+def rt_grid_tree(grid_ptr, depth, density_floor, rel_uniformity, workspace_ptr, workspace_bytes,
+                 keys_ptr, levels_ptr, values_ptr, n_ptr, stream):
+    _check(load().rt_grid_tree(grid_ptr, int(depth), float(density_floor), float(rel_uniformity),
+                               workspace_ptr, int(workspace_bytes), keys_ptr, levels_ptr,
+                               values_ptr, n_ptr, stream), "rt_grid_tree")

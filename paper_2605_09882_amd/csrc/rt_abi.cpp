@@ -273,6 +273,34 @@ int rt_columns_trace(const rt_octree *tree, const double *d_src, int64_t n_src,
 }
 
 // ---------------------------------------------------------------------
+// Contribution grid on the device
+// ---------------------------------------------------------------------
+
+size_t rt_grid_tree_workspace_bytes(int depth) {
+    if (depth < 1 || depth > 10) return 0;
+    return rt::grid_tree_workspace_bytes(depth);
+}
+
+int rt_grid_tree(const double *d_grid, int depth, double density_floor, double rel_uniformity,
+                 void *d_workspace, size_t workspace_bytes, uint64_t *d_keys, uint8_t *d_levels,
+                 double *d_values, int64_t *d_n_leaves, void *stream) {
+    if (depth < 1 || depth > 10) return fail(RT_ERR_ARG, "depth %d not in 1..10", depth);
+    if (!d_grid || !d_keys || !d_levels || !d_values || !d_n_leaves)
+        return fail(RT_ERR_ARG, "null grid or output pointer");
+    if (!std::isfinite(density_floor) || !std::isfinite(rel_uniformity))
+        return fail(RT_ERR_ARG, "density_floor and rel_uniformity must be finite");
+    if (!d_workspace) return fail(RT_ERR_WORKSPACE, "null workspace");
+    if (((uintptr_t)d_workspace & 255) != 0) return fail(RT_ERR_WORKSPACE, "workspace not 256-byte aligned");
+    const size_t need = rt::grid_tree_workspace_bytes(depth);
+    if (workspace_bytes < need)
+        return fail(RT_ERR_WORKSPACE, "workspace has %zu bytes, needs %zu", workspace_bytes, need);
+    hipError_t e = rt::launch_grid_tree(d_grid, depth, density_floor, rel_uniformity, d_workspace,
+                                        d_keys, d_levels, d_values, d_n_leaves,
+                                        static_cast<hipStream_t>(stream));
+    return device_status(e, "grid tree launch");
+}
+
+// ---------------------------------------------------------------------
 // Angular-resolution comparison
 // ---------------------------------------------------------------------
 

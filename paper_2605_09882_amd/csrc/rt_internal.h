@@ -88,6 +88,12 @@ hipError_t launch_nested_reference(const double *fine, const double *coarse, int
                                    int64_t n_src, int64_t ratio, double *ref, double *err,
                                    hipStream_t stream);
 
+// Contribution grid from a uniform grid (rt_grid_tree).
+size_t grid_tree_workspace_bytes(int depth);
+hipError_t launch_grid_tree(const double *grid, int depth, double floor_, double rel,
+                            void *workspace, uint64_t *keys, uint8_t *levels, double *values,
+                            int64_t *n_out, hipStream_t stream);
+
 hipError_t launch_trace(const TreeView &tree, const RayBatch &rays, int32_t *steps,
                         uint64_t *hash, const int64_t *sample, int64_t n_sample,
                         int32_t *visited, int64_t cap, hipStream_t stream);

@@ -94,6 +94,36 @@ class Octree:
                 pass
 
 
+def grid_tree(grid, depth, density_floor, rel_uniformity=0.01):
+    """The contribution grid of the density + uniformity rule, built on the
+    device from a uniform grid (device float64 [8^depth], Morton order).
+    Returns (keys uint64-as-int64, levels uint8, values float64) device
+    tensors of the leaves in Morton order (the count is read back, which
+    synchronises the stream)."""
+    if not torch.is_tensor(grid) or not grid.is_cuda or grid.dtype != torch.float64:
+        raise TypeError("grid must be a float64 device tensor")
+    grid = grid.reshape(-1).contiguous()
+    if grid.numel() != 8 ** depth:
+        raise ValueError(f"grid must hold 8^{depth} values")
+    dev = grid.device
+    nbytes = _abi.rt_grid_tree_workspace_bytes(depth)
+    if nbytes == 0:
+        raise ValueError(f"depth {depth} not in 1..10")
+    ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
+    base = ws.data_ptr()
+    off = (-base) % 256
+    keys = torch.empty(grid.numel(), dtype=torch.int64, device=dev)
+    levels = torch.empty(grid.numel(), dtype=torch.uint8, device=dev)
+    values = torch.empty(grid.numel(), dtype=torch.float64, device=dev)
+    n = torch.empty(1, dtype=torch.int64, device=dev)
+    _abi.rt_grid_tree(grid.data_ptr(), depth, density_floor, rel_uniformity, base + off, nbytes,
+                      keys.data_ptr(), levels.data_ptr(), values.data_ptr(), n.data_ptr(),
+                      _stream(dev))
+    k = int(n.item())
+    del ws
+    return keys[:k], levels[:k], values[:k]
+
+
 def _as_dev(x, dtype, device, shape_last=None):
     if not torch.is_tensor(x):
         x = torch.as_tensor(np.ascontiguousarray(x))

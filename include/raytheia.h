@@ -121,6 +121,18 @@ int rt_build_octree(const uint64_t *keys, const uint8_t *levels, int64_t n_leave
                     int max_depth, void *d_workspace, size_t workspace_bytes, void *stream,
                     rt_octree **out);
 
+/* rt_build_octree for leaf arrays already in device memory (for example the
+ * output of rt_grid_tree): the same checks, made by kernels, and the same
+ * workspace contents.  d_keys [n_leaves] u64 and d_levels [n_leaves] u8 are
+ * device pointers; n_leaves is a host value.  The call waits for the checks
+ * (it synchronises the stream once); the staging is then queued on stream,
+ * and the leaf arrays must stay unchanged until it has run.  Errors as for
+ * rt_build_octree (RT_ERR_UNSORTED names the first unsorted index,
+ * RT_ERR_TILING the first leaf with a tiling error). */
+int rt_build_octree_device(const uint64_t *d_keys, const uint8_t *d_levels, int64_t n_leaves,
+                           int max_depth, void *d_workspace, size_t workspace_bytes, void *stream,
+                           rt_octree **out);
+
 /* Releases the host handle (the workspace stays the caller's). NULL is ok. */
 void rt_octree_free(rt_octree *tree);
 

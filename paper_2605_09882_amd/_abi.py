@@ -33,6 +33,7 @@ EXPORTS = (
     "rt_healpix_dirs_nested",
     "rt_octree_workspace_bytes",
     "rt_build_octree",
+    "rt_build_octree_device",
     "rt_octree_free",
     "rt_octree_leaves",
     "rt_octree_depth",
@@ -77,6 +78,7 @@ def load(path=None):
         "rt_healpix_dirs_nested": (I32, [I32, P]),
         "rt_octree_workspace_bytes": (ctypes.c_size_t, [I64, I32]),
         "rt_build_octree": (I32, [P, P, I64, I32, P, ctypes.c_size_t, V, ctypes.POINTER(V)]),
+        "rt_build_octree_device": (I32, [P, P, I64, I32, P, ctypes.c_size_t, V, ctypes.POINTER(V)]),
         "rt_octree_free": (None, [V]),
         "rt_octree_leaves": (I64, [V]),
         "rt_octree_depth": (I32, [V]),
@@ -138,6 +140,16 @@ def rt_build_octree(keys_ptr, levels_ptr, n_leaves, max_depth, workspace_ptr, wo
     _check(load().rt_build_octree(keys_ptr, levels_ptr, int(n_leaves), int(max_depth),
                                   workspace_ptr, int(workspace_bytes), stream, ctypes.byref(h)),
            "rt_build_octree")
+    return h.value
+
+
+def rt_build_octree_device(keys_ptr, levels_ptr, n_leaves, max_depth, workspace_ptr,
+                           workspace_bytes, stream):
+    """Returns the opaque handle (an int)."""
+    h = ctypes.c_void_p()
+    _check(load().rt_build_octree_device(keys_ptr, levels_ptr, int(n_leaves), int(max_depth),
+                                         workspace_ptr, int(workspace_bytes), stream,
+                                         ctypes.byref(h)), "rt_build_octree_device")
     return h.value
 
 

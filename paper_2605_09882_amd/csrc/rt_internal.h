@@ -88,6 +88,13 @@ hipError_t launch_nested_reference(const double *fine, const double *coarse, int
                                    int64_t n_src, int64_t ratio, double *ref, double *err,
                                    hipStream_t stream);
 
+// Octree staging from device leaf arrays (rt_build_octree_device).
+hipError_t launch_octree_check(const uint64_t *keys, const uint8_t *levels, int64_t n, int depth,
+                               int64_t *status, hipStream_t stream);
+hipError_t launch_octree_stage(const uint64_t *keys, const uint8_t *levels, int64_t n, int depth,
+                               int top_level, void *key_out, uint8_t *level_out, uint32_t *top,
+                               hipStream_t stream);
+
 // Contribution grid from a uniform grid (rt_grid_tree).
 size_t grid_tree_workspace_bytes(int depth);
 hipError_t launch_grid_tree(const double *grid, int depth, double floor_, double rel,

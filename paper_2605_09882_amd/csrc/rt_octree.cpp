@@ -35,6 +35,39 @@ Layout workspace_layout(int64_t n, int depth) {
 // Leaf indices travel in the low 30 bits of a top-table entry.
 constexpr int64_t kMaxLeaves = ((int64_t)1 << 30) - 2;
 
+// The host handle of a tree staged at base with layout lay.
+rt_octree *new_handle(unsigned char *base, const Layout &lay, int64_t n, int depth, int device) {
+    rt_octree *t = new (std::nothrow) rt_octree;
+    if (!t) return nullptr;
+    t->view.keys = base;
+    t->view.levels = base + lay.keys;
+    t->view.top = reinterpret_cast<const uint32_t *>(base + lay.keys + lay.levels);
+    t->view.n = n;
+    t->view.depth = depth;
+    t->view.top_level = rt::top_table_level(depth, n);
+    t->view.wide_keys = depth > 10 ? 1 : 0;
+    t->device = device;
+    return t;
+}
+
+// Argument checks shared by both build calls (everything but the leaves).
+int check_build_args(int64_t n_leaves, int max_depth, void *d_workspace, size_t workspace_bytes,
+                     rt_octree **out) {
+    if (!out) return rt::fail(RT_ERR_ARG, "null output handle pointer");
+    *out = nullptr;
+    if (max_depth < 1 || max_depth > 21)
+        return rt::fail(RT_ERR_ARG, "max_depth %d not in 1..21", max_depth);
+    if (n_leaves < 1 || n_leaves > kMaxLeaves)
+        return rt::fail(RT_ERR_ARG, "n_leaves %lld not in 1..2^30-2", (long long)n_leaves);
+    if (!d_workspace) return rt::fail(RT_ERR_WORKSPACE, "null workspace");
+    if (((uintptr_t)d_workspace & 255) != 0)
+        return rt::fail(RT_ERR_WORKSPACE, "workspace not 256-byte aligned");
+    const size_t need = workspace_layout(n_leaves, max_depth).total();
+    if (workspace_bytes < need)
+        return rt::fail(RT_ERR_WORKSPACE, "workspace has %zu bytes, needs %zu", workspace_bytes, need);
+    return RT_OK;
+}
+
 }  // namespace
 
 namespace rt {
@@ -85,14 +118,10 @@ int rt_build_octree(const uint64_t *keys, const uint8_t *levels, int64_t n_leave
         next = keys[i] + span;
     }
     if (next != end) return fail(RT_ERR_TILING, "leaves end at key %llu, not 8^D", (unsigned long long)next);
-
-    if (!d_workspace) return fail(RT_ERR_WORKSPACE, "null workspace");
-    if (((uintptr_t)d_workspace & 255) != 0) return fail(RT_ERR_WORKSPACE, "workspace not 256-byte aligned");
+    int st = check_build_args(n_leaves, D, d_workspace, workspace_bytes, out);
+    if (st != RT_OK) return st;
     const Layout lay = workspace_layout(n_leaves, D);
     const size_t kb = lay.keys, lb = lay.levels;
-    if (workspace_bytes < lay.total())
-        return fail(RT_ERR_WORKSPACE, "workspace has %zu bytes, needs %zu", workspace_bytes,
-                    lay.total());
 
     // stage keys (+ sentinel), levels and the top table in one host buffer
     std::vector<unsigned char> host(lay.total(), 0);
@@ -141,17 +170,46 @@ int rt_build_octree(const uint64_t *keys, const uint8_t *levels, int64_t n_leave
     e = hipStreamSynchronize(s);  // the staging buffer dies with this call
     if (e != hipSuccess) return device_status(e, "hipStreamSynchronize");
 
-    rt_octree *t = new (std::nothrow) rt_octree;
+    rt_octree *t = new_handle(static_cast<unsigned char *>(d_workspace), lay, n_leaves, D, device);
     if (!t) return fail(RT_ERR_ARG, "out of host memory");
+    *out = t;
+    return ok();
+}
+
+int rt_build_octree_device(const uint64_t *d_keys, const uint8_t *d_levels, int64_t n_leaves,
+                           int max_depth, void *d_workspace, size_t workspace_bytes, void *stream,
+                           rt_octree **out) {
+    int st = check_build_args(n_leaves, max_depth, d_workspace, workspace_bytes, out);
+    if (st != RT_OK) return st;
+    if (!d_keys || !d_levels) return fail(RT_ERR_ARG, "null keys or levels");
+    const int D = max_depth;
+    const Layout lay = workspace_layout(n_leaves, D);
     unsigned char *base = static_cast<unsigned char *>(d_workspace);
-    t->view.keys = base;
-    t->view.levels = base + kb;
-    t->view.top = reinterpret_cast<const uint32_t *>(base + kb + lb);
-    t->view.n = n_leaves;
-    t->view.depth = D;
-    t->view.top_level = lt;
-    t->view.wide_keys = wide ? 1 : 0;
-    t->device = device;
+    uint32_t *top = reinterpret_cast<uint32_t *>(base + lay.keys + lay.levels);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    int device = 0;
+    hipError_t e = hipGetDevice(&device);
+    if (e != hipSuccess) return device_status(e, "hipGetDevice");
+    // the first 16 bytes of the top table's region hold the check results
+    int64_t *status = reinterpret_cast<int64_t *>(top);
+    e = rt::launch_octree_check(d_keys, d_levels, n_leaves, D, status, s);
+    if (e != hipSuccess) return device_status(e, "octree check launch");
+    int64_t found[2];
+    e = hipMemcpyAsync(found, status, sizeof found, hipMemcpyDeviceToHost, s);
+    if (e != hipSuccess) return device_status(e, "hipMemcpyAsync(check)");
+    e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return device_status(e, "hipStreamSynchronize");
+    if (found[0] != INT64_MAX)
+        return fail(RT_ERR_UNSORTED, "keys[%lld] <= keys[%lld]", (long long)found[0],
+                    (long long)(found[0] - 1));
+    if (found[1] != INT64_MAX)
+        return fail(RT_ERR_TILING, "leaf %lld: level above the depth, key not aligned to its level, "
+                    "a gap or an overlap after it, or a first key other than 0", (long long)found[1]);
+    e = rt::launch_octree_stage(d_keys, d_levels, n_leaves, D, rt::top_table_level(D, n_leaves), base,
+                                base + lay.keys, top, s);
+    if (e != hipSuccess) return device_status(e, "octree staging launch");
+    rt_octree *t = new_handle(base, lay, n_leaves, D, device);
+    if (!t) return fail(RT_ERR_ARG, "out of host memory");
     *out = t;
     return ok();
 }

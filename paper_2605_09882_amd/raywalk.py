@@ -80,6 +80,35 @@ class Octree:
                                                 self.depth, base + off, nbytes,
                                                 _stream(self.device))
 
+    @classmethod
+    def from_device(cls, keys, levels, depth):
+        """The octree of leaf arrays already on the device (keys int64 holding
+        the uint64 Morton keys, levels uint8), e.g. from grid_tree(); checked
+        and staged by kernels, without a copy to the host."""
+        if not (torch.is_tensor(keys) and torch.is_tensor(levels) and keys.is_cuda and levels.is_cuda):
+            raise TypeError("keys and levels must be device tensors")
+        if keys.dtype != torch.int64 or levels.dtype != torch.uint8 or keys.shape != levels.shape:
+            raise ValueError("keys must be int64 and levels uint8, of equal length")
+        self = cls.__new__(cls)
+        keys = keys.contiguous()
+        levels = levels.contiguous()
+        self.n = int(keys.numel())
+        self.depth = int(depth)
+        self.device = keys.device
+        nbytes = _abi.rt_octree_workspace_bytes(self.n, self.depth)
+        if nbytes == 0:
+            raise ValueError(f"invalid octree size n={self.n} depth={self.depth}")
+        self._ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        base = self._ws.data_ptr()
+        off = (-base) % 256
+        self._handle = None
+        with torch.cuda.device(self.device):
+            self._handle = _abi.rt_build_octree_device(keys.data_ptr(), levels.data_ptr(), self.n,
+                                                       self.depth, base + off, nbytes,
+                                                       _stream(self.device))
+        self._inputs = (keys, levels)  # kept until the queued staging has run
+        return self
+
     @property
     def handle(self):
         return self._handle

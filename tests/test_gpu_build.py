@@ -108,3 +108,86 @@ def test_merged512_fullsize(rt, orc):
     # the same tree as the workload's host generator, so the same walks
     w = W.make_workload(4)
     assert np.array_equal(got[0], w.tree.keys) and np.array_equal(got[1], w.tree.levels)
+
+
+def _regions(tree):
+    """Bytes of the staged keys, levels and top table of an Octree."""
+    n, D = tree.n, tree.depth
+    ksize = 4 if D <= 10 else 8
+    lt = 0
+    while lt < D and lt < 9 and 8 ** (lt + 1) <= 2 * n:
+        lt += 1
+    al = lambda x: (x + 255) // 256 * 256  # noqa: E731
+    kb, lb = al(ksize * (n + 1)), al(n)
+    off = (-tree._ws.data_ptr()) % 256
+    ws = tree._ws[off:]
+    return (ws[:ksize * (n + 1)], ws[kb:kb + n], ws[kb + lb:kb + lb + 4 * (8 ** lt + 1)])
+
+
+@pytest.mark.parametrize("case", ["random5", "random7", "sparse11", "sparse14", "sparse21", "single"])
+def test_device_octree_equals_host(rt, case):
+    if case.startswith("random"):
+        t = W.random_octree(int(case[6:]), 0.4, 31, min_level=1)
+    elif case == "single":
+        t = W.Octree(3, np.zeros(1, np.uint64), np.zeros(1, np.uint8), np.ones(1))
+    else:
+        t = W.sparse_random_octree(int(case[6:]), 30, 32)
+    dev = torch.device("cuda")
+    host = rt.Octree(t.keys, t.levels, t.depth, dev)
+    k = torch.as_tensor(t.keys.view(np.int64)).to(dev)
+    lv = torch.as_tensor(t.levels).to(dev)
+    devt = rt.Octree.from_device(k, lv, t.depth)
+    torch.cuda.synchronize()
+    for a, b, name in zip(_regions(host), _regions(devt), ("keys", "levels", "top")):
+        assert torch.equal(a, b), (case, name)
+
+
+def test_device_octree_errors(rt):
+    t = W.random_octree(4, 0.5, 41, min_level=1)
+    dev = torch.device("cuda")
+    E = rt._abi
+
+    def build(keys, levels, depth=t.depth):
+        return rt.Octree.from_device(torch.as_tensor(np.asarray(keys, np.uint64).view(np.int64)).to(dev),
+                                     torch.as_tensor(np.asarray(levels, np.uint8)).to(dev), depth)
+
+    def status(keys, levels, depth=t.depth):
+        try:
+            build(keys, levels, depth)
+        except E.RtError as e:
+            return e.status
+        return E.RT_OK
+
+    k, lv = t.keys.copy(), t.levels.copy()
+    sw = k.copy()
+    sw[[3, 4]] = sw[[4, 3]]
+    assert status(sw, lv) == E.RT_ERR_UNSORTED
+    assert status(np.delete(k, 5), np.delete(lv, 5)) == E.RT_ERR_TILING      # gap
+    bad = lv.copy()
+    bad[2] = t.depth + 1
+    assert status(k, bad) == E.RT_ERR_TILING                                  # level > D
+    mis = k.copy()
+    mis[7] += 1
+    assert status(mis, lv) in (E.RT_ERR_TILING, E.RT_ERR_UNSORTED)          # misaligned
+    assert status(k[1:], lv[1:]) == E.RT_ERR_TILING                           # first key not 0
+    assert status(k[:-1], lv[:-1]) == E.RT_ERR_TILING                         # ends early
+    assert status(k, lv) == E.RT_OK
+
+
+def test_grid_to_walk_on_device(rt, orc):
+    """Grid -> tree -> octree handle -> columns, all on the device, equals
+    the same walk over the host-built tree and the oracle."""
+    rho = W.lognormal(W.gaussian_random_field(64, -4.0, 51), 2.0)
+    grid = W.octree.grid_to_morton(rho)
+    floor = float(np.percentile(rho, 70.0))
+    dev = torch.device("cuda")
+    keys, levels, values = rt.grid_tree(torch.as_tensor(grid).to(dev), 6, floor)
+    tree_d = rt.Octree.from_device(keys, levels, 6)
+    ref_tree = W.uniformity_merged_octree(rho, floor, 0.01)
+    src = W.random_points(500, 52)
+    dirs = orc.healpix_ring(2)
+    N_dev, _ = rt.columns(tree_d, values, torch.as_tensor(src).to(dev), torch.as_tensor(dirs).to(dev))
+    ok, ov, oval = orc.grid_tree(grid, 6, floor)
+    ref = orc.columns(W.Octree(6, ok, ov, oval), src, dirs, threads=8)
+    assert np.array_equal(N_dev.cpu().numpy(), ref["N"])
+    assert np.array_equal(ok, ref_tree.keys)

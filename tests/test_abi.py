@@ -138,3 +138,30 @@ def test_walk_calls_reject_null_handles(lib):
     assert lib.rt_octree_leaves(None) == -1
     assert lib.rt_octree_depth(None) == -1
     lib.rt_octree_free(None)
+
+
+def test_new_calls_validate_before_device_work(lib):
+    """The grid construction, the device octree build and the nested
+    reference reject bad arguments on the host, before any device work."""
+    E, W_ = _abi.RT_ERR_ARG, _abi.RT_ERR_WORKSPACE
+    assert _abi.rt_grid_tree_workspace_bytes(0) == 0 and _abi.rt_grid_tree_workspace_bytes(11) == 0
+    assert _abi.rt_grid_tree_workspace_bytes(9) > 8 ** 9 // 7 * 25
+    p = 256  # a fake, aligned, never dereferenced address
+    assert lib.rt_grid_tree(None, 3, 1.0, 0.01, p, 1 << 30, p, p, p, p, None) == E
+    assert lib.rt_grid_tree(p, 0, 1.0, 0.01, p, 1 << 30, p, p, p, p, None) == E
+    assert lib.rt_grid_tree(p, 3, float("inf"), 0.01, p, 1 << 30, p, p, p, p, None) == E
+    assert lib.rt_grid_tree(p, 3, 1.0, 0.01, None, 1 << 30, p, p, p, p, None) == W_
+    assert lib.rt_grid_tree(p, 3, 1.0, 0.01, p + 4, 1 << 30, p, p, p, p, None) == W_
+    assert lib.rt_grid_tree(p, 3, 1.0, 0.01, p, 8, p, p, p, p, None) == W_
+    import ctypes
+    h = ctypes.c_void_p()
+    assert lib.rt_build_octree_device(p, p, 0, 3, p, 1 << 30, None, ctypes.byref(h)) == E
+    assert lib.rt_build_octree_device(p, p, 10, 22, p, 1 << 30, None, ctypes.byref(h)) == E
+    assert lib.rt_build_octree_device(None, p, 10, 3, p, 1 << 30, None, ctypes.byref(h)) == E
+    assert lib.rt_build_octree_device(p, p, 10, 3, p, 16, None, ctypes.byref(h)) == W_
+    assert lib.rt_build_octree_device(p, p, 10, 3, p, 1 << 30, None, None) == E
+    assert h.value is None
+    assert lib.rt_nested_reference(p, 24, p, 12, 1, p, None, None) == E   # ratio 2
+    assert lib.rt_nested_reference(p, 12, p, 48, 1, p, None, None) == E   # fine < coarse
+    assert lib.rt_nested_reference(None, 48, p, 12, 1, p, None, None) == E
+    assert lib.rt_nested_reference(p, 48, None, 12, 1, None, p, None) == E

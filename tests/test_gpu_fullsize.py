@@ -11,8 +11,9 @@ oracle's FP64 gradient on a source subsample, through the linearity
 identity sum_k rho_k dL/drho_k = sum_r g_r N_r on every ray, and against
 FP64 central differences on sampled leaves; (iv) the several-fields walk
 (n_H and three lines) is compared with the oracle on a seeded source
-sample, and on every source A_V,eff lies between the smallest and the mean
-of its directions' extinctions from the FP64 column walk.
+sample of every workload, and on every source A_V,eff lies between the
+smallest and the mean of its directions' extinctions from the FP64 column
+walk.
 """
 
 import numpy as np
@@ -159,7 +160,45 @@ def test_fullsize_adjoint_merged512(rt, orc):
         assert abs(g_full[k] - fd) <= 1e-4 * abs(fd) + 1e-7 * np.abs(g_full).max(), (k, g_full[k], fd)
 
 
-@pytest.mark.parametrize("index", [4, 2])
+@pytest.mark.parametrize("index", [1, 2])
+def test_fullsize_adjoint_identity(rt, orc, index):
+    """The adjoint on the AMR and the uniform 128^3 workloads: the linearity
+    identity on every ray and the oracle's FP64 gradient on a source
+    subsample."""
+    w = _workload(index)
+    dev = torch.device("cuda")
+    dirs, _ = _dirs(rt, orc, w.nside)
+    tree = rt.Octree(w.tree.keys, w.tree.levels, w.tree.depth, dev)
+    src = torch.as_tensor(w.sources).to(dev)
+    dirs_d = torch.as_tensor(dirs).to(dev)
+    S, Dn = src.shape[0], dirs.shape[0]
+    rho32 = torch.as_tensor(w.tree.rho.astype(np.float32)).to(dev)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(3000 + index)
+    wgt = torch.rand((Dn, S), generator=gen, device=dev, dtype=torch.float32).t()
+    _, A = rt.columns(tree, rho32, src, dirs_d, w.kappa)
+    grad = rt.columns_backward(tree, src, dirs_d, w.kappa, gA=wgt, A=A)
+    rho_d = rho32.double()
+    N64, _ = rt.columns(tree, rho_d, src, dirs_d, w.kappa, with_A=False)
+    lhs = float((rho_d * grad).sum())
+    rhs = float((-w.kappa * A.double() * wgt.double() * N64).sum())
+    assert abs(lhs - rhs) <= 1e-6 * abs(rhs), (lhs, rhs)
+    step = max(1, S // 2000)
+    sub = slice(0, S, step)
+    src_s = w.sources[sub]
+    w_s = wgt[sub].cpu().numpy().astype(np.float64)
+    grad_s = rt.columns_backward(tree, torch.as_tensor(src_s).to(dev), dirs_d, w.kappa,
+                                 gA=wgt[sub].contiguous(), A=A[sub].contiguous()).cpu().numpy()
+    rho_w = W.Octree(w.tree.depth, w.tree.keys, w.tree.levels,
+                     w.tree.rho.astype(np.float32).astype(np.float64))
+    ref = orc.columns(rho_w, src_s, dirs, w.kappa, threads=8)
+    want = orc.gradient(rho_w, src_s, dirs, -w.kappa * w_s * ref["A"])
+    scale = np.abs(want).max()
+    assert np.all(np.abs(grad_s - want) <= 1e-5 * np.abs(want) + 1e-6 * scale)
+    torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("index", [4, 2, 1, 3])
 def test_fullsize_shielding(rt, orc, index):
     w = _workload(index)
     dev = torch.device("cuda")

@@ -156,3 +156,29 @@ def test_argument_errors(rt):
                            1 << 3, 1.0, N.data_ptr(), None, 1, 4, s)
     with pytest.raises(ValueError):
         rt.columns(t, rho[:-1].contiguous(), src, dirs)
+
+
+@pytest.mark.parametrize("seed", range(100, 120))
+def test_random_configurations(rt, orc, seed):
+    """Seeded random trees (depth 1..9, random refinement), random sources
+    (with face and corner points) and directions: bit-exact columns, step
+    counts and hashes, and the several-fields walk within its bar."""
+    from gpu_common import assert_shielding
+    rng = np.random.default_rng(seed)
+    depth = int(rng.integers(1, 10))
+    p = float(rng.uniform(0.05, 0.6))
+    tree = W.random_octree(depth, p, seed, min_level=min(int(rng.integers(0, 3)), depth))
+    src = np.vstack([W.random_points(int(rng.integers(1, 400)), seed + 1), edge_sources(depth)])
+    dirs = np.vstack([random_dirs(int(rng.integers(1, 40)), seed + 2), special_dirs()])
+    _compare(rt, orc, tree, src, dirs, kappa=float(rng.uniform(0.1, 3.0)))
+    K = int(rng.integers(1, 9))
+    inp = W.line_inputs(tree, src, K - 1, seed + 3)
+    ref = orc.shielding(tree, inp["fields"], src, dirs, length=inp["length"], temp=inp["temp"],
+                        vturb=inp["vturb"], line_A=inp["line_A"], line_nu=inp["line_nu"], threads=8)
+    dev = torch.device("cuda")
+    t = rt.Octree(tree.keys, tree.levels, tree.depth, dev)
+    got = rt.shielding(t, torch.as_tensor(inp["fields"]).to(dev), torch.as_tensor(src).to(dev),
+                       torch.as_tensor(dirs).to(dev), inp["length"], temp=inp["temp"],
+                       vturb=inp["vturb"], line_A=inp["line_A"], line_nu=inp["line_nu"], rays=True)
+    torch.cuda.synchronize()
+    assert_shielding({k: v.cpu().numpy() for k, v in got.items()}, ref, len(dirs))

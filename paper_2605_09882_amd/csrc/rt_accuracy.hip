@@ -44,7 +44,8 @@ hipError_t launch_nested_reference(const double *fine, const double *coarse, int
                                    hipStream_t stream) {
     const int64_t total = n_coarse * n_src;
     int64_t blocks = (total + kBlock - 1) / kBlock;
-    if (blocks > ((int64_t)1 << 30)) blocks = (int64_t)1 << 30;
+    const int64_t cap = (((int64_t)1 << 32) - 1) / kBlock;  // work items count in 32 bits
+    if (blocks > cap) blocks = cap;
     hipLaunchKernelGGL(k_nested_reference, dim3((unsigned)blocks), dim3(kBlock), 0, stream, fine,
                        coarse, n_coarse, n_src, ratio, ref, err);
     return hipGetLastError();

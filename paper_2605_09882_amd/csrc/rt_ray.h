@@ -320,9 +320,12 @@ inline Tree<KeyT> tree_of(const TreeView &v) {
     return t;
 }
 
+// Blocks for total work items, one per thread: a dispatch counts its work
+// items in 32 bits, so larger launches are capped there and the kernels'
+// grid-stride loops take the rest.
 inline unsigned grid_for(int64_t total) {
     int64_t blocks = (total + kBlock - 1) / kBlock;
-    const int64_t cap = (int64_t)1 << 30;
+    const int64_t cap = (((int64_t)1 << 32) - 1) / kBlock;
     return (unsigned)(blocks < cap ? blocks : cap);
 }
 

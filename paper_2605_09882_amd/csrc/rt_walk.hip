@@ -334,18 +334,19 @@ __global__ __launch_bounds__(kBlock) void k_trace_sample(Tree<KeyT> t, RayBatch 
                                                          int64_t cap, int64_t total) {
     __shared__ uint32_t lut[1 << kLutBits];
     init_lut<KeyT>(lut, t.depth);
-    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= n_sample) return;
-    int32_t *out = visited + j * cap;
-    const int64_t ray = sample[j];
-    int64_t n = 0;
-    if (ray >= 0 && ray < total) {
-        const RayIndex x = ray_index(r, ray);
-        RecordVisits v{out, cap, 0};
-        walk_ray(t, lut, r.src + 3 * x.s, r.dirs + 3 * x.d, v);
-        n = v.n;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n_sample; j += stride) {
+        int32_t *out = visited + j * cap;
+        const int64_t ray = sample[j];
+        int64_t n = 0;
+        if (ray >= 0 && ray < total) {
+            const RayIndex x = ray_index(r, ray);
+            RecordVisits v{out, cap, 0};
+            walk_ray(t, lut, r.src + 3 * x.s, r.dirs + 3 * x.d, v);
+            n = v.n;
+        }
+        for (int64_t e = n; e < cap; ++e) out[e] = -1;
     }
-    for (int64_t e = n; e < cap; ++e) out[e] = -1;
 }
 
 }  // namespace
@@ -406,7 +407,7 @@ hipError_t launch_trace(const TreeView &tree, const RayBatch &rays, int32_t *ste
         if (e != hipSuccess) return e;
     }
     if (n_sample > 0) {
-        const unsigned grid = (unsigned)((n_sample + kBlock - 1) / kBlock);
+        const unsigned grid = grid_for(n_sample);
         if (tree.wide_keys)
             hipLaunchKernelGGL(k_trace_sample<uint64_t>, dim3(grid), dim3(kBlock), 0, stream,
                                tree_of<uint64_t>(tree), rays, sample, n_sample, visited, cap,

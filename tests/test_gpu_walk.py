@@ -182,3 +182,54 @@ def test_random_configurations(rt, orc, seed):
                        vturb=inp["vturb"], line_A=inp["line_A"], line_nu=inp["line_nu"], rays=True)
     torch.cuda.synchronize()
     assert_shielding({k: v.cpu().numpy() for k, v in got.items()}, ref, len(dirs))
+
+
+def test_more_rays_than_one_dispatch(rt, orc):
+    """2^28 sources x 17 directions = 4.56e9 rays, more work items than one
+    dispatch counts (2^32 - 1): the launches cap their grids and stride.
+    Sampled rays beyond index 2^32 (and the last one) against the oracle,
+    bit for bit, with their visited lists, and the adjoint's linearity
+    identity over every ray."""
+    dev = torch.device("cuda")
+    tree = W.random_octree(3, 0.5, 61, min_level=1)
+    rho32_h = tree.rho.astype(np.float32)
+    S, Dn = 1 << 28, 17
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(62)
+    src = torch.rand((S, 3), generator=gen, device=dev, dtype=torch.float64)
+    dirs = random_dirs(Dn, 63)
+    dirs_d = torch.as_tensor(dirs).to(dev)
+    t = rt.Octree(tree.keys, tree.levels, tree.depth, dev)
+    rho32 = torch.as_tensor(rho32_h).to(dev)
+    N32, A32 = rt.columns(t, rho32, src, dirs_d, 1.0)
+    total = S * Dn
+    rng = np.random.default_rng(64)
+    sample = np.concatenate([rng.integers(1 << 32, total, 300), rng.integers(0, total, 100),
+                             [total - 1, (1 << 32) - 1, 1 << 32]]).astype(np.int64)
+    cap = 3 * 8 + 3
+    sample_d = torch.as_tensor(sample).to(dev)
+    visited = torch.empty((len(sample), cap), dtype=torch.int32, device=dev)
+    # the visited lists of the sampled rays only (no per-ray steps or hashes)
+    rt._abi.rt_columns_trace(t.handle, src.data_ptr(), S, dirs_d.data_ptr(), Dn, None, None, 1, S,
+                             sample_d.data_ptr(), len(sample), visited.data_ptr(), cap,
+                             torch.cuda.current_stream().cuda_stream)
+    d_idx, s_idx = np.divmod(sample, S)
+    si = torch.as_tensor(s_idx).to(dev)
+    got = N32[si, torch.as_tensor(d_idx).to(dev)].cpu().numpy()
+    src_h = src[si].cpu().numpy()
+    vis = visited.cpu().numpy()
+    for j in range(len(sample)):
+        r = orc.walk_one(tree, src_h[j], dirs[d_idx[j]], rho32=rho32_h)
+        assert got[j] == np.float32(r["N32"]), (int(sample[j]), got[j], r["N32"])
+        k = len(r["visited"])
+        assert list(vis[j, :k]) == list(r["visited"]) and np.all(vis[j, k:] == -1)
+    del N32
+    # adjoint over every ray: sum_k rho_k grad_k = sum_r g_r N_r, g = -A (w = 1),
+    # with N from the FP64 walk; the sums run one direction at a time
+    ones = torch.ones((Dn, S), dtype=torch.float32, device=dev).t()
+    grad = rt.columns_backward(t, src, dirs_d, 1.0, gA=ones, A=A32)
+    del ones
+    N64, _ = rt.columns(t, rho32.double(), src, dirs_d, 1.0, with_A=False)
+    lhs = float((rho32.double() * grad).sum())
+    rhs = -sum(float((A32[:, d].double() * N64[:, d]).sum()) for d in range(Dn))
+    assert abs(lhs - rhs) <= 1e-6 * abs(rhs), (lhs, rhs)

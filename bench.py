@@ -108,7 +108,8 @@ def stream_copy_gbs(torch, dev, gb):
 
 
 def cpu_baseline(w, dirs_host):
-    """The oracle, single-threaded, on every CPU_SAMPLE_STRIDE-th source."""
+    """The oracle on every CPU_SAMPLE_STRIDE-th source: single-threaded (the
+    reported value), and split over all available cores."""
     import numpy as np
 
     import oracle
@@ -118,10 +119,36 @@ def cpu_baseline(w, dirs_host):
     out = oracle.columns(w.tree, src, dirs_host, w.kappa, rho32=w.tree.rho.astype(np.float32))
     dt = time.perf_counter() - t0
     steps = int(out["steps"].sum())
+    # the same sample split over every core this process may use
+    host = host_cpu()
+    nc = max(1, int(host["cores_available"] or 1))
+    t1 = time.perf_counter()
+    oracle.columns(w.tree, src, dirs_host, w.kappa, rho32=w.tree.rho.astype(np.float32), threads=nc)
+    dt_all = time.perf_counter() - t1
     return {"value": steps / dt, "unit": "ray-leaf steps/s", "cores": 1, "kind": "oracle",
+            "all_cores": {"value": steps / dt_all, "cores": nc},
             "sample": f"every {CPU_SAMPLE_STRIDE}th source ({src.shape[0]} sources x "
                       f"{dirs_host.shape[0]} dirs = {src.shape[0] * dirs_host.shape[0]} rays, "
-                      f"{steps} leaf steps, {dt:.1f} s, FP64 + FP32-Kahan columns)"}
+                      f"{steps} leaf steps, {dt:.1f} s, FP64 + FP32-Kahan columns)",
+            "host": host}
+
+
+def host_cpu():
+    """CPU model and the number of cores this process may run on."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        n = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        n = os.cpu_count()
+    return {"cpu": model, "cores_available": n}
 
 
 def main():

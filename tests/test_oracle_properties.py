@@ -1,0 +1,91 @@
+"""Property tests of the oracle (hypothesis): random tiny octrees from
+random refinement masks, random rays -- generic, snapped to cell faces and
+corners, axis-aligned, and HEALPix directions with their negations.
+
+For every ray: the chords are non-negative and sum to the distance to the
+box boundary; uniform density gives N = rho * distance; the ray and its
+reverse from the same point start in the same leaf and together cover the
+whole line through the box; the FP32-Kahan column is within 1e-5 of FP64 (for columns in
+FP32's normal range); a ray that starts in a leaf visits that leaf first.
+"""
+
+import numpy as np
+from hypothesis import HealthCheck, given, settings
+from hypothesis import strategies as st
+
+import workloads as W
+from reference_geometry import exit_time
+
+SETTINGS = settings(max_examples=60, deadline=None,
+                    suppress_health_check=[HealthCheck.too_slow, HealthCheck.function_scoped_fixture])
+
+
+@st.composite
+def tree_and_ray(draw):
+    depth = draw(st.integers(1, 4))
+    p = draw(st.floats(0.0, 0.9))
+    seed = draw(st.integers(0, 10_000))
+    tree = W.random_octree(depth, p, seed, min_level=draw(st.integers(0, min(2, depth))))
+    side = 1 << depth
+    snap = draw(st.sampled_from(["none", "face", "corner"]))
+    q = np.array([draw(st.floats(0.0, 1.0, exclude_max=True)) for _ in range(3)])
+    if snap != "none":
+        cells = np.floor(q * side)
+        axes = [draw(st.integers(0, 2))] if snap == "face" else [0, 1, 2]
+        for a in axes:
+            q[a] = cells[a] / side
+    kind = draw(st.sampled_from(["random", "axis", "healpix"]))
+    if kind == "random":
+        v = np.array([draw(st.floats(-1.0, 1.0)) for _ in range(3)])
+        if np.linalg.norm(v) < 1e-3:
+            v = np.array([0.3, -0.5, 0.8])
+        m = v / np.linalg.norm(v)
+    elif kind == "axis":
+        m = np.zeros(3)
+        m[draw(st.integers(0, 2))] = draw(st.sampled_from([-1.0, 1.0]))
+    else:
+        import oracle
+        dirs = oracle.healpix_ring(draw(st.sampled_from([1, 2, 4])))
+        m = dirs[draw(st.integers(0, len(dirs) - 1))] * draw(st.sampled_from([-1.0, 1.0]))
+    return tree, q, m
+
+
+@SETTINGS
+@given(tree_and_ray())
+def test_ray_properties(orc, case):
+    tree, q, m = case
+    r = orc.walk_one(tree, q, m, rho32=tree.rho.astype(np.float32))
+    assert r["status"] == orc.OK
+    te = exit_time(q, m)
+    c = r["chords"]
+    assert np.all(c >= 0.0)
+    assert abs(c.sum() - te) <= 1e-12 * max(te, 1e-300) + 1e-15
+    assert abs(r["texit"] - te) <= 1e-12 * max(te, 1e-300) + 1e-15
+    # the first leaf visited holds the source
+    k = orc.morton(*np.floor(q * (1 << tree.depth)).astype(np.int64), tree.depth)
+    first = int(np.searchsorted(tree.keys, np.uint64(k), side="right")) - 1
+    assert r["visited"][0] == first
+    # uniform density: N = rho * distance
+    u = orc.walk_one(tree, q, m, rho=np.full(tree.n, 1.75))
+    assert abs(u["N"] - 1.75 * te) <= 1e-12 * 1.75 * te + 1e-15
+    # FP32-Kahan against FP64, for columns inside FP32's normal range (a
+    # source within 1e-38 of its exit face has a column FP32 cannot hold)
+    if r["N"] > 1e-30:
+        assert abs(float(r["N32"]) - r["N"]) <= 1e-5 * r["N"]
+
+
+@SETTINGS
+@given(tree_and_ray())
+def test_reverse_ray(orc, case):
+    """Walking m and -m from one point covers the whole line through the
+    box: both start in the source's leaf, and with uniform density the two
+    totals add up to the length of the line inside the box."""
+    tree, q, m = case
+    fwd = orc.walk_one(tree, q, m)
+    back = orc.walk_one(tree, q, -m)
+    assert fwd["status"] == orc.OK and back["status"] == orc.OK
+    total = exit_time(q, m) + exit_time(q, -m)
+    assert fwd["visited"][0] == back["visited"][0]
+    u = orc.walk_one(tree, q, m, rho=np.ones(tree.n))["N"] + \
+        orc.walk_one(tree, q, -m, rho=np.ones(tree.n))["N"]
+    assert abs(u - total) <= 1e-12 * total + 1e-15

@@ -9,7 +9,11 @@
  * each leaf by the slab method (sec. 2.3.2), and accumulates
  *     N(p, q) = sum_k rho_k r_k        (the discrete integral of sec. 2.3)
  * and the attenuation A = exp(-kappa N) (solution of the absorption-only
- * transfer equation, sec. 2.1) up to the boundary of the unit box.
+ * transfer equation, sec. 2.1) up to the boundary of the unit box.  Around
+ * that walk: its adjoint, several fields per walk (line optical depths,
+ * escape probabilities and the effective visual extinction, sec. 2.4 and
+ * 3), the angular-resolution comparison of sec. 3, and the construction of
+ * the contribution grid from a uniform grid (sec. 2.4).
  *
  * Conventions (all calls):
  *   - The domain is the unit box [0,1)^3; cells are half-open.  A tree of
@@ -24,9 +28,10 @@
  *   - Every call returns an rt_status (0 = RT_OK, < 0 = error); nothing
  *     throws or aborts.  On error, rt_last_error() gives a message (thread-
  *     local).  Argument checks run synchronously on the host before any
- *     device work is queued; device work is queued on the given stream
- *     (a hipStream_t passed as void*, NULL = the default stream) and runs
- *     asynchronously.
+ *     device work is queued (rt_build_octree_device checks its device leaf
+ *     arrays with a kernel and waits for the result); device work is queued
+ *     on the given stream (a hipStream_t passed as void*, NULL = the default
+ *     stream) and runs asynchronously.
  *   - Calls that launch kernels may run concurrently on different streams,
  *     also on the same octree: the octree is read-only after building.
  */

@@ -34,6 +34,8 @@
  *     stream) and runs asynchronously.
  *   - Calls that launch kernels may run concurrently on different streams,
  *     also on the same octree: the octree is read-only after building.
+ *   - An octree belongs to the device that was current when it was built;
+ *     walk calls with another device current fail with RT_ERR_ARG.
  */
 #ifndef RAYTHEIA_H
 #define RAYTHEIA_H

@@ -43,6 +43,11 @@ int check_rays(const rt_octree *tree, const double *d_src, int64_t n_src, const 
                int64_t n_dirs, int64_t stride_src, int64_t stride_dir, RayBatch *rays) {
     if (!tree) return fail(RT_ERR_ARG, "null octree handle");
     if (!d_src || !d_dirs) return fail(RT_ERR_ARG, "null source or direction pointer");
+    int device = 0;
+    if (hipGetDevice(&device) != hipSuccess) return fail(RT_ERR_DEVICE, "hipGetDevice failed");
+    if (device != tree->device)
+        return fail(RT_ERR_ARG, "the octree lives on device %d, the current device is %d", tree->device,
+                    device);
     if (n_src < 1 || n_dirs < 1) return fail(RT_ERR_ARG, "n_src and n_dirs must be >= 1");
     if (n_src > INT64_MAX / 3 || n_dirs > INT64_MAX / n_src)
         return fail(RT_ERR_ARG, "n_src * n_dirs overflows");

@@ -40,49 +40,6 @@ constexpr int kMaxPeel = 1;
 constexpr int kOwnerSlots = 128;
 
 // ---------------------------------------------------------------------
-// Visitors
-// ---------------------------------------------------------------------
-
-struct SumF64 {
-    const double *__restrict__ rho;
-    double N;
-    __device__ __forceinline__ double fetch(uint32_t i) const { return rho[i]; }
-    __device__ __forceinline__ void step(double r, uint32_t, double l) { N = N + r * l; }
-};
-
-struct SumF32Kahan {
-    const float *__restrict__ rho;
-    float S, c;
-    __device__ __forceinline__ float fetch(uint32_t i) const { return rho[i]; }
-    __device__ __forceinline__ void step(float r, uint32_t, double l) {
-        const float y = r * (float)l - c;
-        const float t = S + y;
-        c = (t - S) - y;
-        S = t;
-    }
-};
-
-struct HashSteps {
-    uint64_t h;
-    __device__ __forceinline__ int fetch(uint32_t) const { return 0; }
-    __device__ __forceinline__ void step(int, uint32_t i, double) {
-        h = (h ^ (uint64_t)i) * 0x100000001b3ull;
-    }
-};
-
-struct RecordVisits {
-    int32_t *__restrict__ out;
-    int64_t cap;
-    int64_t n;
-    __device__ __forceinline__ int fetch(uint32_t) const { return 0; }
-    __device__ __forceinline__ void step(int, uint32_t i, double) {
-        if (n < cap) out[n] = (int32_t)i;
-        ++n;
-    }
-};
-
-
-// ---------------------------------------------------------------------
 // Forward kernels
 // ---------------------------------------------------------------------
 

@@ -165,3 +165,20 @@ def test_new_calls_validate_before_device_work(lib):
     assert lib.rt_nested_reference(p, 12, p, 48, 1, p, None, None) == E   # fine < coarse
     assert lib.rt_nested_reference(None, 48, p, 12, 1, p, None, None) == E
     assert lib.rt_nested_reference(p, 48, None, 12, 1, None, p, None) == E
+
+
+def test_missing_library_fails_loudly(tmp_path):
+    """Without the built library the binding raises; it has no fallback."""
+    with pytest.raises(RuntimeError, match="no CPU fallback"):
+        _abi.load(str(tmp_path / "absent.so"))
+
+
+def test_product_never_touches_the_oracle():
+    """No source of the package or its native code names the oracle, so no
+    call of the product can route through it."""
+    pkg = os.path.join(ROOT, "paper_2605_09882_amd")
+    for base, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".cpp", ".h")):
+                text = open(os.path.join(base, f)).read()
+                assert not re.search(r"\boracle\b|\borc_", text), os.path.join(base, f)

@@ -75,8 +75,18 @@ struct SumFields {
     }
 };
 
+// Waves per SIMD the compiler is asked to fit, by field count (1 sets no
+// bound).  At K = 1 and K = 8 the kernel sits a few registers above a wave
+// boundary (66 and 131 VGPRs with 32-bit keys), and the extra wave costs two
+// spilled registers.  Larger targets at other K, with 8-20 registers
+// spilled, speed up coherent rays but slow down scattered sources more.
+template <int K>
+constexpr int kMinWaves = K == 1 ? 8 : K == 8 ? 4 : 1;
+
 template <typename KeyT, int K>
-__global__ __launch_bounds__(kBlock) void k_shielding(Tree<KeyT> t, const double *__restrict__ src,
+__global__ __launch_bounds__(kBlock)
+__attribute__((amdgpu_waves_per_eu(kMinWaves<K>))) void k_shielding(Tree<KeyT> t,
+                                                      const double *__restrict__ src,
                                                       int64_t n_src, const double *__restrict__ dirs,
                                                       int64_t n_dirs, const double *__restrict__ F,
                                                       ShieldingParams p, double *__restrict__ rays,

@@ -56,7 +56,8 @@ def _inputs(tree, src, n_lines, seed):
 
 
 @pytest.mark.parametrize("depth,p,seed,n_lines", [(1, 0.0, 11, 0), (3, 0.6, 12, 1), (4, 0.5, 13, 3),
-                                                   (5, 0.35, 14, 7), (6, 0.2, 15, 2)])
+                                                   (5, 0.35, 14, 7), (6, 0.2, 15, 2), (4, 0.45, 16, 4),
+                                                   (5, 0.3, 17, 5), (3, 0.5, 18, 6)])
 def test_random_amr_trees(rt, orc, depth, p, seed, n_lines):
     tree = W.random_octree(depth, p, seed, min_level=min(1, depth))
     src = np.vstack([W.random_points(200, seed + 10), edge_sources(depth),

@@ -26,6 +26,22 @@ def _ptr(t):
     return None if t is None else t.data_ptr()
 
 
+def _gpu(device):
+    """device with its index filled in (a bare "cuda" is the current GPU), so
+    that it compares equal to the device of the tensors allocated there."""
+    device = torch.device(device)
+    if device.type == "cuda" and device.index is None:
+        device = torch.device("cuda", torch.cuda.current_device())
+    return device
+
+
+def _same_device(t, dev, name):
+    """The kernels take raw device pointers: a buffer elsewhere (the host or
+    another GPU) must be refused here, before any launch."""
+    if t.device != dev:
+        raise ValueError(f"{name} is on {t.device}, the octree on {dev}")
+
+
 def healpix_npix(nside):
     return _abi.rt_healpix_npix(nside)
 
@@ -66,7 +82,7 @@ class Octree:
             raise ValueError("keys and levels must be 1-D arrays of equal length")
         self.n = int(keys.shape[0])
         self.depth = int(depth)
-        self.device = torch.device(device)
+        self.device = _gpu(device)
         nbytes = _abi.rt_octree_workspace_bytes(self.n, self.depth)
         if nbytes == 0:
             raise ValueError(f"invalid octree size n={self.n} depth={self.depth}")
@@ -89,6 +105,7 @@ class Octree:
             raise TypeError("keys and levels must be device tensors")
         if keys.dtype != torch.int64 or levels.dtype != torch.uint8 or keys.shape != levels.shape:
             raise ValueError("keys must be int64 and levels uint8, of equal length")
+        _same_device(levels, keys.device, "levels")
         self = cls.__new__(cls)
         keys = keys.contiguous()
         levels = levels.contiguous()
@@ -173,6 +190,7 @@ def columns(tree, rho, src, dirs, kappa=1.0, with_A=True):
     if not rho.is_cuda or rho.numel() != tree.n or not rho.is_contiguous():
         raise ValueError("rho must be a contiguous device tensor with one value per leaf")
     dev = tree.device
+    _same_device(rho, dev, "rho")
     src = _as_dev(src, torch.float64, dev, 3)
     dirs = _as_dev(dirs, torch.float64, dev, 3)
     S, Dn = src.shape[0], dirs.shape[0]
@@ -208,6 +226,8 @@ def columns_backward(tree, src, dirs, kappa, gN=None, gA=None, A=None, grad=None
         grad = torch.zeros(tree.n, dtype=torch.float64, device=dev)
     elif grad.dtype != torch.float64 or grad.numel() != tree.n or not grad.is_contiguous():
         raise ValueError("grad must be a contiguous float64 tensor with one value per leaf")
+    else:
+        _same_device(grad, dev, "grad")
     _abi.rt_columns_backward(tree.handle, src.data_ptr(), S, dirs.data_ptr(), Dn, kappa,
                              _ptr(gN), _ptr(gA), _ptr(A), 1, S, grad.data_ptr(), _stream(dev))
     return grad
@@ -256,6 +276,7 @@ def shielding(tree, fields, src, dirs, length, temp=None, vturb=0.0, line_A=(), 
     fields = fields.contiguous()
     if fields.shape[0] != tree.n:
         raise ValueError("fields must hold one row per leaf")
+    _same_device(fields, dev, "fields")
     K = int(fields.shape[1])
     src = _as_dev(src, torch.float64, dev, 3)
     dirs = _as_dev(dirs, torch.float64, dev, 3)

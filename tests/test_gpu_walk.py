@@ -158,6 +158,27 @@ def test_argument_errors(rt):
         rt.columns(t, rho[:-1].contiguous(), src, dirs)
 
 
+def test_buffers_on_another_device_are_refused(rt):
+    """The kernels take raw pointers, so the binding refuses, before any
+    launch, a buffer that is not on the octree's GPU (a host tensor here)."""
+    tree = W.random_octree(3, 0.5, 72, min_level=1)
+    t = rt.Octree(tree.keys, tree.levels, tree.depth, "cuda")
+    assert t.device == torch.device("cuda", torch.cuda.current_device())
+    src = torch.rand(4, 3, dtype=torch.float64)
+    dirs = random_dirs(2, 1)
+    g = torch.ones(4, 2, dtype=torch.float32)
+    with pytest.raises(ValueError, match="grad is on cpu"):
+        rt.columns_backward(t, src, dirs, 1.0, gN=g, grad=torch.zeros(tree.n, dtype=torch.float64))
+    with pytest.raises(ValueError):
+        rt.columns(t, torch.as_tensor(tree.rho), src, dirs)
+    with pytest.raises(TypeError):
+        rt.shielding(t, torch.as_tensor(tree.rho), src, dirs, 1.0)
+    # the same calls with device buffers run
+    grad = rt.columns_backward(t, src, dirs, 1.0, gN=g)
+    torch.cuda.synchronize()
+    assert grad.device == t.device and bool(torch.isfinite(grad).all())
+
+
 @pytest.mark.parametrize("seed", range(100, 120))
 def test_random_configurations(rt, orc, seed):
     """Seeded random trees (depth 1..9, random refinement), random sources

@@ -136,3 +136,43 @@ def test_adjoint_amr128_vs_oracle_sample(rt, orc):
     ref = orc.columns(w3.tree, src, dirs, w3.kappa, threads=8)
     want = orc.gradient(w3.tree, src, dirs, -w3.kappa * w * ref["A"])
     _close(grad, want, 1e-5, 1e-6)
+
+
+@pytest.mark.parametrize("S,Dn", [(1, 1), (63, 5), (65, 12), (257, 3), (1000, 1)])
+def test_adjoint_ragged_sizes(rt, orc, S, Dn):
+    """Ray counts that leave the last wavefront and block partly empty: the
+    lockstep adjoint loop must neither lose nor double any ray."""
+    tree = W.random_octree(4, 0.45, 40 + S, min_level=1)
+    src = W.random_points(S, 41 + S)
+    dirs = random_dirs(Dn, 42 + Dn)
+    w = np.random.default_rng(43 + S).random((S, Dn))
+    grad, _, _ = _loss_grad(rt, tree, src, dirs, w, 1.0)
+    ref = orc.columns(tree, src, dirs, 1.0)
+    want = orc.gradient(tree, src, dirs, -w * ref["A"])
+    _close(grad, want, 1e-5, 1e-6)
+
+
+def test_adjoint_invalid_and_zero_rays(rt, orc):
+    """Sources outside the box give NaN columns and no gradient; rays with a
+    zero upstream gradient add nothing; a gradient given with strides other
+    than the library's layout is rearranged by the binding.  The result is
+    the oracle's gradient over the valid rays alone."""
+    tree = W.random_octree(4, 0.5, 51, min_level=1)
+    good = W.random_points(150, 52)
+    bad = np.array([[1.0, 0.5, 0.5], [0.5, -1e-300, 0.5], [0.25, 0.5, 1.5]])
+    src = np.vstack([good[:70], bad, good[70:]])
+    valid = np.ones(len(src), bool)
+    valid[70:73] = False
+    dirs = np.vstack([orc.healpix_ring(1), random_dirs(3, 53)])
+    rng = np.random.default_rng(54)
+    gN = rng.standard_normal((len(src), len(dirs)))
+    gN[rng.random(gN.shape) < 0.3] = 0.0
+    dev = torch.device("cuda")
+    t = rt.Octree(tree.keys, tree.levels, tree.depth, dev)
+    src_d, dirs_d = torch.as_tensor(src).to(dev), torch.as_tensor(dirs).to(dev)
+    N, _ = rt.columns(t, torch.as_tensor(tree.rho).to(dev, torch.float32), src_d, dirs_d, 1.0)
+    assert bool(torch.isnan(N[70:73]).all()) and not bool(torch.isnan(N[valid]).any())
+    g_src_major = torch.as_tensor(gN).to(dev, torch.float32).contiguous()  # strides (Dn, 1)
+    grad = rt.columns_backward(t, src_d, dirs_d, 1.0, gN=g_src_major)
+    want = orc.gradient(tree, src[valid], dirs, gN[valid])
+    _close(grad.cpu().numpy(), want, 1e-5, 1e-6)

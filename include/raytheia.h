@@ -35,7 +35,10 @@
  *   - Calls that launch kernels may run concurrently on different streams,
  *     also on the same octree: the octree is read-only after building.
  *   - An octree belongs to the device that was current when it was built;
- *     walk calls with another device current fail with RT_ERR_ARG.
+ *     walk calls with another device current fail with RT_ERR_ARG.  Their
+ *     device pointers must address memory of that device: the kernels
+ *     dereference them as they are, and the library cannot tell a host or
+ *     foreign pointer from its own (a wrong one faults the GPU).
  */
 #ifndef RAYTHEIA_H
 #define RAYTHEIA_H

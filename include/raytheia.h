@@ -219,6 +219,27 @@ int rt_columns_backward(const rt_octree *tree, const double *d_src, int64_t n_sr
                         const float *d_gA, const float *d_A, int64_t stride_src,
                         int64_t stride_dir, double *d_grad_rho, void *stream);
 
+/* rt_columns (RT_FP32_KAHAN) and rt_columns_backward in one pass, for a loss
+ * linear in N and A whose weights are known before the walk:
+ *     L = sum over rays of (wN * N + wA * A),  so  g = wN - kappa * A * wA.
+ * Each ray is walked for its column, N and A are stored, and the ray is
+ * walked again to scatter g * r_k (the same two walks as the separate
+ * calls, fused so that the second finds the leaves of the first in cache).
+ *   d_rho    device f32 [n_leaves] leaf values;
+ *   d_wN, d_wA  device f32 weights at the rt_columns offsets, or NULL (= 0);
+ *   d_N      device f32 output; d_A device f32 output or NULL;
+ *   d_grad_rho device f64 [n_leaves], accumulated (the caller zeroes it).
+ * N and A have the bits of rt_columns with RT_FP32_KAHAN; the gradient is
+ * that of rt_columns_backward with d_gN = d_wN, d_gA = d_wA and the same A,
+ * up to the order of its additions.  Invalid rays give N = A = NaN and add
+ * nothing.  With both weights NULL only the forward runs.
+ * Errors: RT_ERR_ARG, RT_ERR_DEVICE. */
+int rt_columns_with_adjoint(const rt_octree *tree, const float *d_rho, const double *d_src,
+                            int64_t n_src, const double *d_dirs, int64_t n_dirs, double kappa,
+                            const float *d_wN, const float *d_wA, float *d_N, float *d_A,
+                            int64_t stride_src, int64_t stride_dir, double *d_grad_rho,
+                            void *stream);
+
 /* Traversal record of every ray, for verification: the number of leaves
  * visited and a 64-bit FNV-1a-style hash of the visited leaf indices
  * (h = 0xcbf29ce484222325; per leaf index i: h = (h ^ i) * 0x100000001b3 mod

@@ -10,7 +10,8 @@ passes torch device tensors and the current stream to it.
 """
 
 from . import _abi
-from .raywalk import (Octree, RayColumns, columns, columns_backward, columns_trace, grid_tree,
+from .raywalk import (Octree, RayColumns, columns, columns_backward, columns_trace,
+                      columns_with_adjoint, grid_tree,
                       healpix_dirs, healpix_dirs_nested, healpix_npix, ray_columns, shielding)
 
 __all__ = [
@@ -19,6 +20,7 @@ __all__ = [
     "RayColumns",
     "columns",
     "columns_backward",
+    "columns_with_adjoint",
     "columns_trace",
     "grid_tree",
     "healpix_dirs",

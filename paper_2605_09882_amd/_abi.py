@@ -39,6 +39,7 @@ EXPORTS = (
     "rt_octree_depth",
     "rt_columns",
     "rt_columns_backward",
+    "rt_columns_with_adjoint",
     "rt_columns_trace",
     "rt_shielding",
     "rt_nested_reference",
@@ -84,6 +85,7 @@ def load(path=None):
         "rt_octree_depth": (I32, [V]),
         "rt_columns": (I32, [V, P, I32, P, I64, P, I64, D, P, P, I64, I64, V]),
         "rt_columns_backward": (I32, [V, P, I64, P, I64, D, P, P, P, I64, I64, P, V]),
+        "rt_columns_with_adjoint": (I32, [V, P, P, I64, P, I64, D, P, P, P, P, I64, I64, P, V]),
         "rt_columns_trace": (I32, [V, P, I64, P, I64, P, P, I64, I64, P, I64, P, I64, V]),
         "rt_shielding": (I32, [V, P, I32, P, I64, P, I64, D, P, D, P, P, D, D, P, P, P, V]),
         "rt_nested_reference": (I32, [P, I64, P, I64, I64, P, P, V]),
@@ -177,6 +179,13 @@ def rt_columns_backward(handle, src_ptr, n_src, dirs_ptr, n_dirs, kappa, gN_ptr,
     _check(load().rt_columns_backward(handle, src_ptr, int(n_src), dirs_ptr, int(n_dirs),
                                       float(kappa), gN_ptr, gA_ptr, A_ptr, int(stride_src),
                                       int(stride_dir), grad_ptr, stream), "rt_columns_backward")
+
+
+def rt_columns_with_adjoint(handle, rho_ptr, src_ptr, n_src, dirs_ptr, n_dirs, kappa, wN_ptr, wA_ptr,
+                            N_ptr, A_ptr, stride_src, stride_dir, grad_ptr, stream):
+    _check(load().rt_columns_with_adjoint(handle, rho_ptr, src_ptr, int(n_src), dirs_ptr, int(n_dirs),
+                                          float(kappa), wN_ptr, wA_ptr, N_ptr, A_ptr, int(stride_src),
+                                          int(stride_dir), grad_ptr, stream), "rt_columns_with_adjoint")
 
 
 def rt_columns_trace(handle, src_ptr, n_src, dirs_ptr, n_dirs, steps_ptr, hash_ptr, stride_src,

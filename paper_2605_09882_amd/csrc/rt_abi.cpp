@@ -261,6 +261,27 @@ int rt_columns_backward(const rt_octree *tree, const double *d_src, int64_t n_sr
     return device_status(e, "adjoint walk launch");
 }
 
+int rt_columns_with_adjoint(const rt_octree *tree, const float *d_rho, const double *d_src,
+                            int64_t n_src, const double *d_dirs, int64_t n_dirs, double kappa,
+                            const float *d_wN, const float *d_wA, float *d_N, float *d_A,
+                            int64_t stride_src, int64_t stride_dir, double *d_grad_rho,
+                            void *stream) {
+    rt::RayBatch rays;
+    int st = check_rays(tree, d_src, n_src, d_dirs, n_dirs, stride_src, stride_dir, &rays);
+    if (st != RT_OK) return st;
+    if (!d_rho || !d_N) return fail(RT_ERR_ARG, "null rho or N");
+    if (!d_grad_rho) return fail(RT_ERR_ARG, "null gradient output");
+    if (!std::isfinite(kappa)) return fail(RT_ERR_ARG, "kappa not finite");
+    hipError_t e;
+    if (!d_wN && !d_wA)  // zero loss weights: the forward alone
+        e = rt::launch_forward(tree->view, rays, d_rho, RT_FP32_KAHAN, kappa, d_N, d_A,
+                               static_cast<hipStream_t>(stream));
+    else
+        e = rt::launch_forward_adjoint(tree->view, rays, d_rho, kappa, d_wN, d_wA, d_N, d_A,
+                                       d_grad_rho, static_cast<hipStream_t>(stream));
+    return device_status(e, "forward and adjoint walk launch");
+}
+
 int rt_columns_trace(const rt_octree *tree, const double *d_src, int64_t n_src,
                      const double *d_dirs, int64_t n_dirs, int32_t *d_steps, uint64_t *d_hash,
                      int64_t stride_src, int64_t stride_dir, const int64_t *d_sample,

@@ -67,6 +67,10 @@ hipError_t launch_backward(const TreeView &tree, const RayBatch &rays, double ka
                            const float *gN, const float *gA, const float *A, double *grad,
                            hipStream_t stream);
 
+hipError_t launch_forward_adjoint(const TreeView &tree, const RayBatch &rays, const float *rho,
+                                  double kappa, const float *wN, const float *wA, float *N, float *A,
+                                  double *grad, hipStream_t stream);
+
 // Several fields per leaf (rt_shielding): at most kMaxFields fields, field 0
 // the hydrogen density, fields 1.. the population terms of the lines.
 constexpr int kMaxFields = 8;

@@ -183,29 +183,95 @@ __device__ __forceinline__ void flush_table(uint32_t *tag, float *sum, double *_
     }
 }
 
+// Per-wavefront aggregation state of the adjoint: the table, its owner
+// cells, and the steps since the last flush.
+struct AggTable {
+    uint32_t *tag;
+    float *sum;
+    uint32_t *owner;
+    int since_flush;
+};
+
+// The adjoint walk of the wavefront's rays, in lockstep (loop condition
+// uniform over the wavefront, so that all 64 lanes take part in the
+// wavefront-wide sums and in every flush): each step of an active lane adds
+// g * l to its leaf.  st holds the lane's ray, set up by the caller.
+template <typename KeyT>
+__device__ __forceinline__ void scatter_rays(const Tree<KeyT> &t, const uint32_t *lut, Ray &st,
+                                             bool active, float g, int max_steps, AggTable &agg,
+                                             double *__restrict__ grad, int lane) {
+    while (__any(active)) {
+        uint32_t leaf = kEmpty;
+        float v = 0.0f;
+        if (active) {
+            double l;
+            bool done;
+            int level;
+            leaf = ray_locate(st, t, lut, level);
+            ray_advance(st, t, level, l, done);
+            v = g * (float)l;
+            if (done || st.steps >= max_steps) active = false;
+        }
+        // all 64 lanes are active here: sum the groups of lanes that share a
+        // leaf (coarse leaves hold many rays at once)
+        bool pending = leaf != kEmpty;
+        bool cand = pending;  // not yet examined for a shared leaf
+        for (int peel = 0; peel < kMaxPeel; ++peel) {
+            const uint64_t cm = __ballot(cand);
+            if (cm == 0) break;
+            const int leader = __ffsll((unsigned long long)cm) - 1;
+            const uint32_t L = (uint32_t)__builtin_amdgcn_readlane((int)leaf, leader);
+            const bool mine = cand && leaf == L;
+            if (__popcll(__ballot(mine)) >= kPeelMin) {
+                const float total = wave_total(mine ? v : 0.0f);
+                if (mine) {
+                    // the group's total travels in the leader's lane
+                    v = lane == leader ? total : 0.0f;
+                    pending = lane == leader;
+                }
+            }
+            if (mine) cand = false;
+        }
+        table_add(agg.tag, agg.sum, agg.owner, grad, leaf, v, pending, lane);
+        if (++agg.since_flush == kFlushEvery) {
+            flush_table(agg.tag, agg.sum, grad, lane);
+            agg.since_flush = 0;
+        }
+    }
+}
+
+// The LDS of the adjoint kernels: the Morton spread table and one
+// aggregation table per wavefront.
+struct AdjointShared {
+    uint32_t lut[1 << kLutBits];
+    uint32_t tag[kWaves][kAggSlots];
+    float sum[kWaves][kAggSlots];
+    uint32_t owner[kWaves][kOwnerSlots];
+};
+
+template <typename KeyT>
+__device__ __forceinline__ AggTable init_adjoint(AdjointShared &sh, int depth, int wave, int lane) {
+    AggTable agg{sh.tag[wave], sh.sum[wave], sh.owner[wave], 0};
+    for (int j = lane; j < kAggSlots; j += 64) {
+        agg.tag[j] = kEmpty;
+        agg.sum[j] = 0.0f;
+    }
+    init_lut<KeyT>(sh.lut, depth);  // ends with a block barrier
+    return agg;
+}
+
 template <typename KeyT>
 __global__ __launch_bounds__(kBlock) void k_backward(Tree<KeyT> t, RayBatch r, float kappa,
                                                      const float *__restrict__ gN,
                                                      const float *__restrict__ gA,
                                                      const float *__restrict__ A,
                                                      double *__restrict__ grad, int64_t total) {
-    __shared__ uint32_t lut[1 << kLutBits];
-    __shared__ uint32_t s_tag[kWaves][kAggSlots];
-    __shared__ float s_sum[kWaves][kAggSlots];
-    __shared__ uint32_t s_owner[kWaves][kOwnerSlots];
+    __shared__ AdjointShared sh;
     const int wave = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
-    uint32_t *tag = s_tag[wave];
-    float *sum = s_sum[wave];
-    uint32_t *owner = s_owner[wave];
-    for (int j = lane; j < kAggSlots; j += 64) {
-        tag[j] = kEmpty;
-        sum[j] = 0.0f;
-    }
-    init_lut<KeyT>(lut, t.depth);  // ends with a block barrier
+    AggTable agg = init_adjoint<KeyT>(sh, t.depth, wave, lane);
     const int max_steps = 3 * (1 << t.depth) + 3;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    int since_flush = 0;
     // base is uniform over the wavefront: all its lanes run every iteration
     for (int64_t base = (int64_t)blockIdx.x * blockDim.x + (wave << 6); base < total;
          base += stride) {
@@ -219,46 +285,81 @@ __global__ __launch_bounds__(kBlock) void k_backward(Tree<KeyT> t, RayBatch r, f
             if (gA) g = g - kappa * A[x.off] * gA[x.off];
             if (g != 0.0f) active = ray_init(st, t.depth, r.src + 3 * x.s, r.dirs + 3 * x.d);
         }
+        scatter_rays(t, sh.lut, st, active, g, max_steps, agg, grad, lane);
+    }
+    flush_table(agg.tag, agg.sum, grad, lane);
+}
+
+// ---------------------------------------------------------------------
+// Forward and adjoint in one pass, for a loss linear in N and A:
+// L = sum_r (wN_r N_r + wA_r A_r), so g_r = wN_r - kappa A_r wA_r is known as
+// soon as the ray's forward walk ends.  A wavefront walks its rays for the
+// FP32-Kahan column (the bits of k_forward_f32k), stores N and A, and walks
+// them again to scatter g * l; both walks step in lockstep and share the ray
+// state.  The second walk finds the leaves of the first still in cache, and
+// the scatter of some wavefronts overlaps the walks of others.  Asked for 7
+// waves per SIMD (the adjoint's LDS allows 7 blocks per CU), the compiler
+// fits it in 72 VGPRs without spilling; left alone it takes 76 and 6 waves.
+// ---------------------------------------------------------------------
+
+__device__ __noinline__ float exp_f32(float x) { return expf(x); }
+
+template <typename KeyT>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(7, 8))) void k_forward_adjoint(
+    Tree<KeyT> t, RayBatch r, const float *__restrict__ rho, float kappa,
+    const float *__restrict__ wN, const float *__restrict__ wA, float *__restrict__ N,
+    float *__restrict__ A, double *__restrict__ grad, int64_t total) {
+    __shared__ AdjointShared sh;
+    const int wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    AggTable agg = init_adjoint<KeyT>(sh, t.depth, wave, lane);
+    const int max_steps = 3 * (1 << t.depth) + 3;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t base = (int64_t)blockIdx.x * blockDim.x + (wave << 6); base < total;
+         base += stride) {
+        const int64_t ray = base + lane;
+        Ray st;
+        RayIndex x{0, 0, 0};
+        bool valid = false;
+        if (ray < total) {
+            x = ray_index(r, ray);
+            valid = ray_init(st, t.depth, r.src + 3 * x.s, r.dirs + 3 * x.d);
+        }
+        // forward: the FP32-Kahan column, as SumF32Kahan in walk_ray
+        SumF32Kahan v{rho, 0.0f, 0.0f};
+        bool active = valid;
+        bool too_long = false;
         while (__any(active)) {
-            uint32_t leaf = kEmpty;
-            float v = 0.0f;
             if (active) {
                 double l;
                 bool done;
                 int level;
-                leaf = ray_locate(st, t, lut, level);
+                const uint32_t leaf = ray_locate(st, t, sh.lut, level);
+                const float value = v.fetch(leaf);
                 ray_advance(st, t, level, l, done);
-                v = g * (float)l;
-                if (done || st.steps >= max_steps) active = false;
-            }
-            // all 64 lanes are active here: sum the groups of lanes that
-            // share a leaf (coarse leaves hold many rays at once)
-            bool pending = leaf != kEmpty;
-            bool cand = pending;  // not yet examined for a shared leaf
-            for (int peel = 0; peel < kMaxPeel; ++peel) {
-                const uint64_t cm = __ballot(cand);
-                if (cm == 0) break;
-                const int leader = __ffsll((unsigned long long)cm) - 1;
-                const uint32_t L = (uint32_t)__builtin_amdgcn_readlane((int)leaf, leader);
-                const bool mine = cand && leaf == L;
-                if (__popcll(__ballot(mine)) >= kPeelMin) {
-                    const float total = wave_total(mine ? v : 0.0f);
-                    if (mine) {
-                        // the group's total travels in the leader's lane
-                        v = lane == leader ? total : 0.0f;
-                        pending = lane == leader;
-                    }
+                v.step(value, leaf, l);
+                if (done) {
+                    active = false;
+                } else if (st.steps >= max_steps) {
+                    active = false;
+                    too_long = true;
                 }
-                if (mine) cand = false;
-            }
-            table_add(tag, sum, owner, grad, leaf, v, pending, lane);
-            if (++since_flush == kFlushEvery) {
-                flush_table(tag, sum, grad, lane);
-                since_flush = 0;
             }
         }
+        float g = 0.0f;
+        if (ray < total) {
+            const float n = valid && !too_long ? v.S : (float)NAN;
+            const float a = exp_f32(-kappa * n);
+            N[x.off] = n;
+            if (A) A[x.off] = a;
+            if (wN) g = wN[x.off];
+            if (wA) g = g - kappa * a * wA[x.off];
+            active = valid && !too_long && g != 0.0f &&
+                     ray_init(st, t.depth, r.src + 3 * x.s, r.dirs + 3 * x.d);
+        }
+        scatter_rays(t, sh.lut, st, active, g, max_steps, agg, grad, lane);
     }
-    flush_table(tag, sum, grad, lane);
+    flush_table(agg.tag, agg.sum, grad, lane);
 }
 
 // ---------------------------------------------------------------------
@@ -345,6 +446,22 @@ hipError_t launch_backward(const TreeView &tree, const RayBatch &rays, double ka
     else
         hipLaunchKernelGGL(k_backward<uint32_t>, dim3(grid), dim3(kBlock), 0, stream,
                            tree_of<uint32_t>(tree), rays, (float)kappa, gN, gA, A, grad, total);
+    return hipGetLastError();
+}
+
+hipError_t launch_forward_adjoint(const TreeView &tree, const RayBatch &rays, const float *rho,
+                                  double kappa, const float *wN, const float *wA, float *N, float *A,
+                                  double *grad, hipStream_t stream) {
+    const int64_t total = rays.n_src * rays.n_dirs;
+    const unsigned grid = grid_for(total);
+    if (tree.wide_keys)
+        hipLaunchKernelGGL(k_forward_adjoint<uint64_t>, dim3(grid), dim3(kBlock), 0, stream,
+                           tree_of<uint64_t>(tree), rays, rho, (float)kappa, wN, wA, N, A, grad,
+                           total);
+    else
+        hipLaunchKernelGGL(k_forward_adjoint<uint32_t>, dim3(grid), dim3(kBlock), 0, stream,
+                           tree_of<uint32_t>(tree), rays, rho, (float)kappa, wN, wA, N, A, grad,
+                           total);
     return hipGetLastError();
 }
 

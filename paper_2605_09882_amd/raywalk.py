@@ -233,6 +233,40 @@ def columns_backward(tree, src, dirs, kappa, gN=None, gA=None, A=None, grad=None
     return grad
 
 
+def columns_with_adjoint(tree, rho, src, dirs, kappa, wN=None, wA=None, grad=None):
+    """FP32-Kahan (N, A) and, in the same pass, dL/drho for the loss
+    L = sum(wN * N) + sum(wA * A) with weights known in advance.
+
+    rho: device float32 [n_leaves]; wN, wA: [S, Dn] weights or None.
+    Returns (N, A, grad): N and A [S, Dn] views with the bits of columns(),
+    grad float64 [n_leaves] (added into grad when given).  The result is that
+    of columns() followed by columns_backward(gN=wN, gA=wA); one kernel walks
+    each ray twice, the second time with its leaves still in cache."""
+    if rho.dtype != torch.float32:
+        raise TypeError("rho must be float32 (the FP32-Kahan walk)")
+    if not rho.is_cuda or rho.numel() != tree.n or not rho.is_contiguous():
+        raise ValueError("rho must be a contiguous device tensor with one value per leaf")
+    dev = tree.device
+    _same_device(rho, dev, "rho")
+    src = _as_dev(src, torch.float64, dev, 3)
+    dirs = _as_dev(dirs, torch.float64, dev, 3)
+    S, Dn = src.shape[0], dirs.shape[0]
+    wN = _dir_major_f32(wN, S, Dn, dev)
+    wA = _dir_major_f32(wA, S, Dn, dev)
+    if grad is None:
+        grad = torch.zeros(tree.n, dtype=torch.float64, device=dev)
+    elif grad.dtype != torch.float64 or grad.numel() != tree.n or not grad.is_contiguous():
+        raise ValueError("grad must be a contiguous float64 tensor with one value per leaf")
+    else:
+        _same_device(grad, dev, "grad")
+    N = torch.empty((Dn, S), dtype=torch.float32, device=dev)
+    A = torch.empty((Dn, S), dtype=torch.float32, device=dev)
+    _abi.rt_columns_with_adjoint(tree.handle, rho.data_ptr(), src.data_ptr(), S, dirs.data_ptr(), Dn,
+                                 kappa, _ptr(wN), _ptr(wA), N.data_ptr(), A.data_ptr(), 1, S,
+                                 grad.data_ptr(), _stream(dev))
+    return N.t(), A.t(), grad
+
+
 def columns_trace(tree, src, dirs, sample=None, cap=0):
     """Per ray: leaves visited (int32) and the FNV hash of their indices
     (int64 holding the uint64 bits), as [S, Dn] views; plus, for the ray ids

@@ -133,6 +133,8 @@ def test_walk_calls_reject_null_handles(lib):
         _abi.RT_ERR_ARG
     assert lib.rt_columns_trace(None, 1, 1, 1, 1, 1, 1, 1, 1, None, 0, None, 0, None) == \
         _abi.RT_ERR_ARG
+    assert lib.rt_columns_with_adjoint(None, 1, 1, 1, 1, 1, 1.0, 1, None, 1, None, 1, 1, 1, None) == \
+        _abi.RT_ERR_ARG
     assert lib.rt_shielding(None, 1, 1, 1, 1, 1, 1, 1.0, None, 0.0, None, None, 3.02, 6.29e-22, None,
                             1, None, None) == _abi.RT_ERR_ARG
     assert lib.rt_octree_leaves(None) == -1

@@ -1,0 +1,176 @@
+"""The forward and its adjoint in one pass (rt_columns_with_adjoint) for a
+loss linear in N and A, against the separate calls and the oracle.
+
+Bars: N and A bit-identical to rt_columns (RT_FP32_KAHAN); the gradient
+within 1e-5 relative of the oracle's FP64 gradient (floor 1e-6 max|grad|),
+as for rt_columns_backward, and within the same bar of the separate
+rt_columns_backward call, whose additions run in another order.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from gpu_common import edge_sources, random_dirs, require_gpu, special_dirs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def rt():
+    return require_gpu()
+
+
+def _close(got, want, rel=1e-5, floor=1e-6):
+    scale = np.abs(want).max()
+    err = np.abs(got - want)
+    bad = np.nonzero(err > rel * np.abs(want) + floor * scale)[0]
+    assert len(bad) == 0, f"{len(bad)} of {len(want)} leaves off"
+
+
+def _same(a, b):
+    """Equal values, NaN where the other has NaN (invalid rays)."""
+    return np.array_equal(a.cpu().numpy(), b.cpu().numpy(), equal_nan=True)
+
+
+def _run(rt, orc, tree, src, dirs, kappa, wN, wA):
+    dev = torch.device("cuda")
+    t = rt.Octree(tree.keys, tree.levels, tree.depth, dev)
+    r32 = torch.as_tensor(tree.rho.astype(np.float32)).to(dev)
+    src_d, dirs_d = torch.as_tensor(src).to(dev), torch.as_tensor(dirs).to(dev)
+    tw = lambda x: None if x is None else torch.as_tensor(x).to(dev, torch.float32)  # noqa: E731
+    N, A, grad = rt.columns_with_adjoint(t, r32, src_d, dirs_d, kappa, wN=tw(wN), wA=tw(wA))
+    N0, A0 = rt.columns(t, r32, src_d, dirs_d, kappa)
+    assert _same(N, N0) and _same(A, A0), "N and A differ from rt_columns"
+    sep = rt.columns_backward(t, src_d, dirs_d, kappa, gN=tw(wN), gA=tw(wA), A=A0)
+    torch.cuda.synchronize()
+    got, sep = grad.cpu().numpy(), sep.cpu().numpy()
+    valid = ~np.isnan(N0.cpu().numpy()).any(axis=1)
+    ref = orc.columns(tree, src[valid], dirs, kappa, rho32=tree.rho.astype(np.float32))
+    g = np.zeros((int(valid.sum()), len(dirs)))
+    if wN is not None:
+        g = g + wN[valid]
+    if wA is not None:
+        g = g - kappa * ref["A32"].astype(np.float64) * wA[valid]
+    want = orc.gradient(tree, src[valid], dirs, g)
+    _close(got, want)
+    _close(got, sep)
+    return got
+
+
+@pytest.mark.parametrize("seed,depth,p", [(1, 4, 0.5), (2, 6, 0.2), (3, 7, 0.1)])
+def test_random_trees(rt, orc, seed, depth, p):
+    tree = W.random_octree(depth, p, seed, min_level=1)
+    src = np.vstack([W.random_points(300, seed + 1), edge_sources(depth)])
+    dirs = np.vstack([orc.healpix_ring(2), special_dirs(), random_dirs(5, seed + 2)])
+    rng = np.random.default_rng(seed + 3)
+    wA = rng.random((len(src), len(dirs)))
+    wN = rng.standard_normal((len(src), len(dirs)))
+    _run(rt, orc, tree, src, dirs, 0.8, None, wA)
+    _run(rt, orc, tree, src, dirs, 1.1, wN, wA)
+    _run(rt, orc, tree, src, dirs, 1.0, wN, None)
+
+
+@pytest.mark.parametrize("S,Dn", [(1, 1), (63, 5), (65, 12), (257, 3)])
+def test_ragged_sizes(rt, orc, S, Dn):
+    tree = W.random_octree(4, 0.45, 60 + S, min_level=1)
+    src = W.random_points(S, 61 + S)
+    dirs = random_dirs(Dn, 62 + Dn)
+    wA = np.random.default_rng(63 + S).random((S, Dn))
+    _run(rt, orc, tree, src, dirs, 1.0, None, wA)
+
+
+def test_invalid_sources_and_zero_weights(rt, orc):
+    """Sources outside the box get N = A = NaN and add nothing; zero weights
+    add nothing."""
+    tree = W.random_octree(4, 0.5, 71, min_level=1)
+    good = W.random_points(120, 72)
+    src = np.vstack([good[:50], [[1.0, 0.5, 0.5], [0.5, -1e-300, 0.5]], good[50:]])
+    dirs = orc.healpix_ring(1)
+    rng = np.random.default_rng(73)
+    wA = rng.random((len(src), len(dirs)))
+    wA[rng.random(wA.shape) < 0.3] = 0.0
+    _run(rt, orc, tree, src, dirs, 1.0, None, wA)
+
+
+def test_deep_tree_wide_keys(rt, orc):
+    tree = W.sparse_random_octree(14, 30, 81)
+    src = W.random_points(200, 82)
+    dirs = np.vstack([orc.healpix_ring(1), special_dirs()])
+    wA = np.random.default_rng(83).random((len(src), len(dirs)))
+    _run(rt, orc, tree, src, dirs, 1.0, None, wA)
+
+
+def test_without_weights_only_the_forward_runs(rt):
+    tree = W.random_octree(3, 0.5, 91, min_level=1)
+    dev = torch.device("cuda")
+    t = rt.Octree(tree.keys, tree.levels, tree.depth, dev)
+    r32 = torch.as_tensor(tree.rho.astype(np.float32)).to(dev)
+    src = torch.as_tensor(W.random_points(70, 92)).to(dev)
+    dirs = torch.as_tensor(random_dirs(3, 93)).to(dev)
+    grad = torch.full((tree.n,), 2.5, dtype=torch.float64, device=dev)
+    N, A, g = rt.columns_with_adjoint(t, r32, src, dirs, 1.0, grad=grad)
+    N0, A0 = rt.columns(t, r32, src, dirs, 1.0)
+    torch.cuda.synchronize()
+    assert torch.equal(N, N0) and torch.equal(A, A0)
+    assert g is grad and bool((grad == 2.5).all())
+
+
+def test_argument_errors(rt):
+    tree = W.random_octree(3, 0.5, 95, min_level=1)
+    dev = torch.device("cuda")
+    t = rt.Octree(tree.keys, tree.levels, tree.depth, dev)
+    r32 = torch.as_tensor(tree.rho.astype(np.float32)).to(dev)
+    src = torch.rand(4, 3, dtype=torch.float64, device=dev)
+    dirs = torch.as_tensor(random_dirs(2, 96)).to(dev)
+    buf = torch.empty(8, dtype=torch.float32, device=dev)
+    grad = torch.zeros(tree.n, dtype=torch.float64, device=dev)
+    s = torch.cuda.current_stream().cuda_stream
+    lib = rt._abi.load()
+    E = rt._abi.RT_ERR_ARG
+    args = [t.handle, r32.data_ptr(), src.data_ptr(), 4, dirs.data_ptr(), 2, 1.0, buf.data_ptr(),
+            None, buf.data_ptr(), None, 1, 4, grad.data_ptr(), s]
+    for i, v in ((1, None), (9, None), (13, None), (6, float("nan")), (3, 0), (11, -1)):
+        a = list(args)
+        a[i] = v
+        assert lib.rt_columns_with_adjoint(*a) == E, i
+    with pytest.raises(TypeError):
+        rt.columns_with_adjoint(t, r32.double(), src, dirs, 1.0, wA=torch.ones(4, 2))
+
+
+def test_merged512_fullsize(rt, orc):
+    """The benchmark's pass at full size (1.6e9 rays): N and A bit-identical to
+    rt_columns on every ray, the gradient equal to the separate adjoint's
+    within 1e-5 (the order of additions differs), the identity
+    sum_k rho_k grad_k = sum_r g_r N_r over every ray, and the oracle's
+    gradient of a 1/4096 source subsample walked by both paths."""
+    w = W.make_workload(4)
+    dev = torch.device("cuda")
+    t = rt.Octree(w.tree.keys, w.tree.levels, w.tree.depth, dev)
+    r32 = torch.as_tensor(w.tree.rho.astype(np.float32)).to(dev)
+    src = torch.as_tensor(w.sources).to(dev)
+    dirs = torch.as_tensor(rt.healpix_dirs(w.nside)).to(dev)
+    S, Dn = src.shape[0], dirs.shape[0]
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(3004)
+    wA = torch.rand((Dn, S), device=dev, generator=gen).t()
+    N, A, grad = rt.columns_with_adjoint(t, r32, src, dirs, w.kappa, wA=wA)
+    N0, A0 = rt.columns(t, r32, src, dirs, w.kappa)
+    assert torch.equal(N, N0) and torch.equal(A, A0)
+    del N0
+    sep = rt.columns_backward(t, src, dirs, w.kappa, gA=wA, A=A0)
+    _close(grad.cpu().numpy(), sep.cpu().numpy())
+    g = -w.kappa * A.double() * wA.double()
+    rhs = float((g * N.double()).sum())
+    lhs = float((r32.double() * grad).sum())
+    assert abs(lhs - rhs) <= 1e-6 * abs(rhs)
+    # the oracle on a subsample: both paths on those sources only
+    sub = w.sources[::4096]
+    wsub = wA[::4096].cpu().numpy().astype(np.float64)
+    _, _, gsub = rt.columns_with_adjoint(t, r32, torch.as_tensor(sub).to(dev), dirs, w.kappa,
+                                         wA=torch.as_tensor(wsub).to(dev, torch.float32))
+    ref = orc.columns(w.tree, sub, dirs.cpu().numpy(), w.kappa, rho32=w.tree.rho.astype(np.float32),
+                      threads=8)
+    want = orc.gradient(w.tree, sub, dirs.cpu().numpy(), -w.kappa * ref["A32"].astype(np.float64) * wsub)
+    _close(gsub.cpu().numpy(), want)

@@ -21,7 +21,8 @@ def lib():
 
 
 def declared_functions():
-    text = open(HEADER).read()
+    with open(HEADER) as f:
+        text = f.read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
     return sorted(set(re.findall(r"\b(rt_[a-z0-9_]+)\s*\(", text)))
 
@@ -182,5 +183,6 @@ def test_product_never_touches_the_oracle():
     for base, _, files in os.walk(pkg):
         for f in files:
             if f.endswith((".py", ".hip", ".cpp", ".h")):
-                text = open(os.path.join(base, f)).read()
+                with open(os.path.join(base, f)) as fh:
+                    text = fh.read()
                 assert not re.search(r"\boracle\b|\borc_", text), os.path.join(base, f)

@@ -8,9 +8,13 @@ centres in the 12 HEALPix directions (nside = 1), about 1.6e9 rays.
 One step = one pass of the whole hot path over that batch: the HEALPix
 direction table, the FP32-Kahan forward walk (N and A = exp(-kappa N)), and
 the adjoint walk of L = sum w A (w ~ U(0,1) per ray) scattering dL/drho onto
-the leaves.  The value is ray-leaf steps per second of that pass: the leaf
-visits of the forward walk (the adjoint re-walks the same ones) divided by
-the time of the pass.  The FP64 walk over the same rays, and the
+the leaves, both in the one kernel of rt_columns_with_adjoint (each
+wavefront walks its rays for N and A, then walks them again to scatter).
+The value is ray-leaf steps per second of that pass: the leaf visits of the
+forward walk (the adjoint re-walks the same ones) divided by the time of the
+pass.  The same pass as two calls (rt_columns, then rt_columns_backward, the
+path of the autograd function) is timed after it; the FP64 walk over the
+same rays, and the
 several-fields walk (n_H and three lines: per-source escape probabilities
 and A_V,eff), and the construction of the contribution grid from the 512^3
 grid on the device, are timed after the pass and reported beside it.
@@ -32,8 +36,10 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0
 VALU_PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9  # CUs x SIMDs x lanes x clock
 CPU_SAMPLE_STRIDE = 4096
-BYTES_PER_STEP = {"k_forward_f32k": 13, "k_forward_f64": 17, "k_backward": 25}
-BYTES_PER_RAY = {"k_forward_f32k": 32, "k_forward_f64": 40, "k_backward": 32}
+BYTES_PER_STEP = {"k_forward_f32k": 13, "k_forward_f64": 17, "k_backward": 25,
+                  "k_forward_adjoint": 38}
+BYTES_PER_RAY = {"k_forward_f32k": 32, "k_forward_f64": 40, "k_backward": 32,
+                 "k_forward_adjoint": 36}
 # several-fields walk: n_H and three lines (key 8 + level 1 + 8 per field per step)
 SHIELD_LINES = 3
 SHIELD_BYTES_PER_STEP = 9 + 8 * (1 + SHIELD_LINES)
@@ -205,24 +211,30 @@ def main():
 
     def one_step(marks=None):
         d = torch.as_tensor(rt.healpix_dirs(w.nside)).to(dev, non_blocking=False)
-        if marks:
-            marks[0].record()
-        N, A = rt.columns(tree, rho32, src, d, kappa)
-        if marks:
-            marks[1].record()
         grad.zero_()
         if marks:
-            marks[2].record()
-        rt.columns_backward(tree, src, d, kappa, gA=wgt, A=A, grad=grad)
+            marks[0].record()
+        N, A, _ = rt.columns_with_adjoint(tree, rho32, src, d, kappa, wA=wgt, grad=grad)
         if marks:
-            marks[3].record()
+            marks[1].record()
+        return N, A
+
+    def separate_step(marks):
+        d = torch.as_tensor(rt.healpix_dirs(w.nside)).to(dev, non_blocking=False)
+        marks[0].record()
+        N, A = rt.columns(tree, rho32, src, d, kappa)
+        marks[1].record()
+        grad.zero_()
+        marks[2].record()
+        rt.columns_backward(tree, src, d, kappa, gA=wgt, A=A, grad=grad)
+        marks[3].record()
         return N, A
 
     for _ in range(args.warmup):
         one_step()
     torch.cuda.synchronize()
 
-    marks = [[ev() for _ in range(4)] for _ in range(args.steps)]
+    marks = [[ev() for _ in range(2)] for _ in range(args.steps)]
     start, stop = ev(), ev()
     torch.cuda.synchronize()
     t_wall = time.perf_counter()
@@ -235,10 +247,21 @@ def main():
     t_gpu = start.elapsed_time(stop) / 1e3
     t_total = max(t_wall, t_gpu)
     ms_step = 1e3 * t_total / args.steps
-    fwd_ms = float(np.mean([m[0].elapsed_time(m[1]) for m in marks]))
-    bwd_ms = float(np.mean([m[2].elapsed_time(m[3]) for m in marks]))
+    fused_ms = float(np.mean([m[0].elapsed_time(m[1]) for m in marks]))
     value = total_steps * args.steps / t_total
-    log(f"step {ms_step:.1f} ms: forward {fwd_ms:.1f} ms, adjoint {bwd_ms:.1f} ms")
+    log(f"step {ms_step:.1f} ms: forward and adjoint in one kernel {fused_ms:.1f} ms")
+
+    # the same pass as two calls (the autograd function's path)
+    separate_step([ev() for _ in range(4)])
+    torch.cuda.synchronize()
+    smarks = [[ev() for _ in range(4)] for _ in range(args.steps)]
+    for k in range(args.steps):
+        separate_step(smarks[k])
+    torch.cuda.synchronize()
+    fwd_ms = float(np.mean([m[0].elapsed_time(m[1]) for m in smarks]))
+    bwd_ms = float(np.mean([m[2].elapsed_time(m[3]) for m in smarks]))
+    sep_ms = float(np.mean([m[0].elapsed_time(m[3]) for m in smarks]))
+    log(f"separate calls {sep_ms:.1f} ms: forward {fwd_ms:.1f} ms, adjoint {bwd_ms:.1f} ms")
 
     # FP64 walk of the same rays, for comparison
     fp64 = None
@@ -335,18 +358,14 @@ def main():
             f"(same as the host tree: {same}); octree handle from the device arrays in "
             f"{build['octree_from_device_ms']:.2f} ms")
 
-    # roofline of the dominant kernel: algorithmic bytes per launch over its
-    # measured duration.  Per ray-leaf step the method reads one leaf record
-    # (Morton key 8 B, level 1 B, value 4 B FP32 / 8 B FP64); the adjoint
-    # reads key and level and adds into an FP64 gradient (8 B read + 8 B
-    # written).  Per ray: the source (24 B) plus N and A (FP32), or the
-    # upstream gradient and A read by the adjoint.
-    fwd_bytes = total_steps * BYTES_PER_STEP["k_forward_f32k"] + rays * BYTES_PER_RAY["k_forward_f32k"]
-    bwd_bytes = total_steps * BYTES_PER_STEP["k_backward"] + rays * BYTES_PER_RAY["k_backward"]
-    if bwd_ms >= fwd_ms:
-        kname, kms, kbytes = "k_backward", bwd_ms, bwd_bytes
-    else:
-        kname, kms, kbytes = "k_forward_f32k", fwd_ms, fwd_bytes
+    # roofline of the pass's kernel: algorithmic bytes per launch over its
+    # measured duration.  Per ray-leaf step the forward reads one leaf record
+    # (Morton key 8 B, level 1 B, value 4 B FP32), and the adjoint reads key
+    # and level again and adds into an FP64 gradient (8 B read + 8 B
+    # written): 38 B.  Per ray: the source (24 B), N and A written (FP32) and
+    # the loss weight read.
+    kname, kms = "k_forward_adjoint", fused_ms
+    kbytes = total_steps * BYTES_PER_STEP[kname] + rays * BYTES_PER_RAY[kname]
     achieved = kbytes / (kms / 1e3) / 1e9
     src_hash = kernel_source_hash()
     prof = stored_counters(kname, w.name, src_hash)
@@ -368,6 +387,7 @@ def main():
 
     line = {
         "metric": "ray-leaf steps/sec (FP32-Kahan forward + adjoint pass; FP64 walk beside it)",
+        "pass": "forward and adjoint in one kernel (rt_columns_with_adjoint)",
         "value": value,
         "unit": "ray-leaf steps/s",
         "n_gpus": 1,
@@ -382,6 +402,9 @@ def main():
         "config": {"workload": w.name, "leaves": w.tree.n, "sources": S, "directions": Dn,
                    "rays": rays, "ray_leaf_steps": total_steps, "kappa": kappa,
                    "parallelism": "single GPU"},
+        "fused_kernel_ms": round(fused_ms, 3),
+        "separate_calls": {"ms": round(sep_ms, 3), "steps_per_s": total_steps / (sep_ms / 1e3),
+                           "note": "rt_columns then rt_columns_backward (the autograd path)"},
         "forward_ms": round(fwd_ms, 3),
         "adjoint_ms": round(bwd_ms, 3),
         "fp32k_forward_steps_per_s": total_steps / (fwd_ms / 1e3),

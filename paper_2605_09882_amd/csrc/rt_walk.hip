@@ -28,6 +28,7 @@ constexpr int kWaves = kBlock / 64;
 constexpr int kAggSlots = 512;
 constexpr int kAggWays = 4;
 constexpr int kAggSets = kAggSlots / kAggWays;
+static_assert(kAggWays == 4, "a set's tags are read as one uint4");
 constexpr int kFlushEvery = 16;
 constexpr uint32_t kEmpty = 0xffffffffu;
 // Before the table, lanes that share a leaf in the same step are summed
@@ -146,12 +147,14 @@ __device__ __forceinline__ void table_add(uint32_t *tag, float *sum, uint32_t *o
     int claim = -1;
     if (pending) {
         const int set = (int)(leaf & (kAggSets - 1)) * kAggWays;
+        // the set's 4 tags in one 16-byte LDS read (sets are 16-byte aligned)
+        const uint4 ways = *reinterpret_cast<const uint4 *>(tag + set);
+        const uint32_t tgs[kAggWays] = {ways.x, ways.y, ways.z, ways.w};
         int empty = -1;
 #pragma unroll
         for (int way = 0; way < kAggWays; ++way) {
-            const uint32_t tg = tag[set + way];
-            if (tg == leaf) slot = set + way;
-            if (tg == kEmpty && empty < 0) empty = set + way;
+            if (tgs[way] == leaf) slot = set + way;
+            if (tgs[way] == kEmpty && empty < 0) empty = set + way;
         }
         claim = slot < 0 && empty >= 0 ? empty : -1;
     }
@@ -242,10 +245,10 @@ __device__ __forceinline__ void scatter_rays(const Tree<KeyT> &t, const uint32_t
 
 // The LDS of the adjoint kernels: the Morton spread table and one
 // aggregation table per wavefront.
-struct AdjointShared {
-    uint32_t lut[1 << kLutBits];
+struct alignas(16) AdjointShared {
     uint32_t tag[kWaves][kAggSlots];
     float sum[kWaves][kAggSlots];
+    uint32_t lut[1 << kLutBits];
     uint32_t owner[kWaves][kOwnerSlots];
 };
 

@@ -198,8 +198,11 @@ struct AggTable {
 // The adjoint walk of the wavefront's rays, in lockstep (loop condition
 // uniform over the wavefront, so that all 64 lanes take part in the
 // wavefront-wide sums and in every flush): each step of an active lane adds
-// g * l to its leaf.  st holds the lane's ray, set up by the caller.
-template <typename KeyT>
+// g * l to its leaf.  st holds the lane's ray, set up by the caller.  Peel:
+// sum the largest group of lanes on one leaf across the wavefront first (it
+// pays in the adjoint alone; in the fused pass, where the walks of other
+// wavefronts keep the VALU busy, it costs more than it saves).
+template <bool Peel, typename KeyT>
 __device__ __forceinline__ void scatter_rays(const Tree<KeyT> &t, const uint32_t *lut, Ray &st,
                                              bool active, float g, int max_steps, AggTable &agg,
                                              double *__restrict__ grad, int lane) {
@@ -219,7 +222,7 @@ __device__ __forceinline__ void scatter_rays(const Tree<KeyT> &t, const uint32_t
         // leaf (coarse leaves hold many rays at once)
         bool pending = leaf != kEmpty;
         bool cand = pending;  // not yet examined for a shared leaf
-        for (int peel = 0; peel < kMaxPeel; ++peel) {
+        for (int peel = 0; Peel && peel < kMaxPeel; ++peel) {
             const uint64_t cm = __ballot(cand);
             if (cm == 0) break;
             const int leader = __ffsll((unsigned long long)cm) - 1;
@@ -288,7 +291,7 @@ __global__ __launch_bounds__(kBlock) void k_backward(Tree<KeyT> t, RayBatch r, f
             if (gA) g = g - kappa * A[x.off] * gA[x.off];
             if (g != 0.0f) active = ray_init(st, t.depth, r.src + 3 * x.s, r.dirs + 3 * x.d);
         }
-        scatter_rays(t, sh.lut, st, active, g, max_steps, agg, grad, lane);
+        scatter_rays<true>(t, sh.lut, st, active, g, max_steps, agg, grad, lane);
     }
     flush_table(agg.tag, agg.sum, grad, lane);
 }
@@ -360,7 +363,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(7, 8))) 
             active = valid && !too_long && g != 0.0f &&
                      ray_init(st, t.depth, r.src + 3 * x.s, r.dirs + 3 * x.d);
         }
-        scatter_rays(t, sh.lut, st, active, g, max_steps, agg, grad, lane);
+        scatter_rays<false>(t, sh.lut, st, active, g, max_steps, agg, grad, lane);
     }
     flush_table(agg.tag, agg.sum, grad, lane);
 }

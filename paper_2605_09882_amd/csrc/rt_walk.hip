@@ -305,9 +305,11 @@ __global__ __launch_bounds__(kBlock) void k_backward(Tree<KeyT> t, RayBatch r, f
 // state.  The second walk finds the leaves of the first still in cache, and
 // the scatter of some wavefronts overlaps the walks of others.  Asked for 7
 // waves per SIMD (the adjoint's LDS allows 7 blocks per CU), the compiler
-// fits it in 72 VGPRs without spilling; left alone it takes 76 and 6 waves.
+// fits it in 72 VGPRs without spilling.
 // ---------------------------------------------------------------------
 
+// Out of line, as exp_f64: inlined, its constants would stay live across
+// both walks.
 __device__ __noinline__ float exp_f32(float x) { return expf(x); }
 
 template <typename KeyT>

@@ -29,12 +29,20 @@ def fnv_sequence_hash(indices):
 
 
 def exit_time(Q, m):
-    """t at which Q + m t leaves [0,1]^3 (axes with m_a == 0 never bound)."""
+    """t at which Q + m t leaves [0,1]^3.  An axis bounds iff 1/m_a is finite:
+    m_a = 0 never bounds, and neither does a subnormal m_a (the reading of
+    rays parallel to an axis that the walk follows; it differs from the
+    exact geometry only for a source closer to the face such an axis would
+    leave through than |m_a|, that is on it or a subnormal distance away)."""
     t = np.inf
     for a in range(3):
+        with np.errstate(divide="ignore", over="ignore"):
+            bounding = np.isfinite(1.0 / m[a])
+        if not bounding:
+            continue
         if m[a] > 0:
             t = min(t, (1.0 - Q[a]) / m[a])
-        elif m[a] < 0:
+        else:
             t = min(t, (0.0 - Q[a]) / m[a])
     return t
 

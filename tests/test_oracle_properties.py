@@ -89,3 +89,16 @@ def test_reverse_ray(orc, case):
     u = orc.walk_one(tree, q, m, rho=np.ones(tree.n))["N"] + \
         orc.walk_one(tree, q, -m, rho=np.ones(tree.n))["N"]
     assert abs(u - total) <= 1e-12 * total + 1e-15
+
+
+def test_subnormal_component_never_bounds(orc):
+    """A subnormal direction component has no finite reciprocal, so its axis
+    does not bound (the reading of rays parallel to an axis): the ray from
+    the origin along (0, 1, -2.2e-311) runs to y = 1 instead of leaving
+    through z = 0 at t = 0."""
+    tree = W.random_octree(1, 0.0, 0)
+    m = np.array([0.0, 1.0, -2.22507386e-311])
+    r = orc.walk_one(tree, np.zeros(3), m)
+    assert r["status"] == orc.OK
+    assert exit_time(np.zeros(3), m) == 1.0
+    assert r["texit"] == 1.0 and r["chords"].sum() == 1.0

@@ -16,7 +16,9 @@ from hypothesis import strategies as st
 import workloads as W
 from reference_geometry import exit_time
 
-SETTINGS = settings(max_examples=60, deadline=None,
+# derandomize: the same examples on every run, so that the suite's verdict
+# does not depend on the run (explicit tests keep the cases found earlier)
+SETTINGS = settings(max_examples=400, deadline=None, derandomize=True,
                     suppress_health_check=[HealthCheck.too_slow, HealthCheck.function_scoped_fixture])
 
 

@@ -174,3 +174,26 @@ def test_merged512_fullsize(rt, orc):
                       threads=8)
     want = orc.gradient(w.tree, sub, dirs.cpu().numpy(), -w.kappa * ref["A32"].astype(np.float64) * wsub)
     _close(gsub.cpu().numpy(), want)
+
+
+def test_A_output_is_optional(rt):
+    """With d_A = NULL the kernel still forms A for g = -kappa A wA; the
+    gradient equals the one of the call that stores A."""
+    tree = W.random_octree(4, 0.4, 97, min_level=1)
+    dev = torch.device("cuda")
+    t = rt.Octree(tree.keys, tree.levels, tree.depth, dev)
+    r32 = torch.as_tensor(tree.rho.astype(np.float32)).to(dev)
+    S, Dn = 300, 12
+    src = torch.as_tensor(W.random_points(S, 98)).to(dev)
+    dirs = torch.as_tensor(random_dirs(Dn, 99)).to(dev)
+    wA = torch.rand((Dn, S), device=dev)
+    N = torch.empty((Dn, S), dtype=torch.float32, device=dev)
+    g1 = torch.zeros(tree.n, dtype=torch.float64, device=dev)
+    s = torch.cuda.current_stream().cuda_stream
+    rt._abi.rt_columns_with_adjoint(t.handle, r32.data_ptr(), src.data_ptr(), S, dirs.data_ptr(), Dn,
+                                    1.0, None, wA.data_ptr(), N.data_ptr(), None, 1, S,
+                                    g1.data_ptr(), s)
+    N2, _, g2 = rt.columns_with_adjoint(t, r32, src, dirs, 1.0, wA=wA.t())
+    torch.cuda.synchronize()
+    assert torch.equal(N.t(), N2)
+    _close(g1.cpu().numpy(), g2.cpu().numpy())

@@ -51,9 +51,11 @@ def build(source=None, output=None):
     """Compile the oracle with gcc (always recompiles).  source/output let a
     test compile a copy with a planted mistake somewhere else."""
     out = output or _LIB
-    cmd = ["gcc", *_CFLAGS, source or _SRC, "-o", out + ".tmp", "-lm"]
+    # a temporary name per process: parallel test workers may build at once
+    tmp = f"{out}.tmp{os.getpid():x}"
+    cmd = ["gcc", *_CFLAGS, source or _SRC, "-o", tmp, "-lm"]
     subprocess.run(cmd, check=True)
-    os.replace(out + ".tmp", out)
+    os.replace(tmp, out)
     return out
 
 

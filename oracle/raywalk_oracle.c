@@ -104,55 +104,69 @@ int orc_healpix_ring(int nside, double *dirs)
     return ORC_OK;
 }
 
-/* NESTED order (Gorski et al. 2005): pixel p = f nside^2 + i lies on base
- * pixel f; the even bits of i give its x and the odd bits its y coordinate
- * on the face.  The face's southmost corner is on ring face_row[f] nside at
- * azimuth face_col[f] pi / 4; pixel (x, y) then lies on ring
- * face_row nside - x - y - 1, at position (face_col n_r + x - y + 1 + s) / 2
- * (1-based) in that ring, with n_r the ring's pixel count over 4 and s = 1
- * for the belt rings whose centres sit on integer multiples of the azimuth
- * step.  The centre is the RING table's centre of that (ring, position). */
+/* NESTED order (Gorski et al. 2005), through the continuous HEALPix
+ * projection of the sphere onto the plane (the projection that defines the
+ * pixelisation; in its equatorial zone the plane coordinates are phi and
+ * 3 pi z / 8, in its polar zones a point at sigma = sqrt(3 (1 - |z|)) keeps
+ * its distance from the polar tooth's centre meridian scaled by sigma).
+ * Here the plane is measured in units of pi/4: X = 4 phi / pi, Y = 4 y / pi.
+ * Every base pixel is then a square of diagonal 2 turned by 45 degrees,
+ * centred where the nside = 1 RING centres lie (z = 2/3, 0, -2/3 give
+ * Y = 1, 0, -1; phi = pi/4 + k pi/2 or k pi/2 gives X = 1 + 2k or 2k):
+ *   faces 0..3  (north)   centre (1 + 2f, 1),
+ *   faces 4..7  (equator) centre (2 (f - 4), 0),
+ *   faces 8..11 (south)   centre (1 + 2 (f - 8), -1).
+ * Pixel p = f nside^2 + i: the even bits of i give its x and the odd bits
+ * its y coordinate on the face; x runs from the face's south corner toward
+ * its east corner, y toward its west corner, so the centre of (x, y) is
+ *   X = Xc + (x - y) / nside,  Y = Yc - 1 + (x + y + 1) / nside.
+ * Back onto the sphere: |Y| <= 1 (equatorial zone) gives z = 2 Y / 3 and
+ * phi = pi X / 4; |Y| > 1 (polar zone) gives sigma = 2 - |Y|,
+ * z = sign(Y) (1 - sigma^2 / 3) and phi = (pi / 4) (Xc + (X - Xc) / sigma),
+ * Xc being the tooth's centre meridian, which is the face's own for a polar
+ * face (the polar part of a north or south face lies inside its tooth). */
 int orc_healpix_nested(int nside, double *dirs)
 {
-    static const int face_row[12] = {2, 2, 2, 2, 3, 3, 3, 3, 4, 4, 4, 4};
-    static const int face_col[12] = {1, 3, 5, 7, 0, 2, 4, 6, 1, 3, 5, 7};
     int64_t npix = orc_healpix_npix(nside);
     if (npix < 0 || !dirs || (nside & (nside - 1))) return ORC_ERR_ARG;
-    double *ring = (double *)malloc(sizeof(double) * 3 * npix);
-    if (!ring) return ORC_ERR_ARG;
-    orc_healpix_ring(nside, ring);
-    const int64_t N = nside;
+    const double pi = 3.14159265358979323846;
+    const double ns = (double)nside;
+    const int64_t per_face = (int64_t)nside * (int64_t)nside;
     for (int64_t p = 0; p < npix; ++p) {
-        int f = (int)(p / (N * N));
-        int64_t in_face = p % (N * N), x = 0, y = 0;
+        int f = (int)(p / per_face);
+        int64_t in_face = p % per_face, x = 0, y = 0;
         for (int b = 0; b < 32; ++b) {
             x |= ((in_face >> (2 * b)) & 1) << b;
             y |= ((in_face >> (2 * b + 1)) & 1) << b;
         }
-        int64_t ring_i = face_row[f] * N - x - y - 1;  /* 1-based from the north */
-        int64_t nr, s, start;
-        if (ring_i < N) {                  /* north cap: 4 ring_i pixels */
-            nr = ring_i;
-            s = 0;
-            start = 2 * ring_i * (ring_i - 1);
-        } else if (ring_i <= 3 * N) {      /* belt: 4 N pixels */
-            nr = N;
-            s = (ring_i - N) % 2;
-            start = 2 * N * (N - 1) + (ring_i - N) * 4 * N;
-        } else {                           /* south cap */
-            nr = 4 * N - ring_i;
-            s = 0;
-            start = npix - 2 * nr * (nr + 1);
+        double Xc, Yc;
+        if (f < 4) {
+            Xc = 1.0 + 2.0 * f;
+            Yc = 1.0;
+        } else if (f < 8) {
+            Xc = 2.0 * (f - 4);
+            Yc = 0.0;
+        } else {
+            Xc = 1.0 + 2.0 * (f - 8);
+            Yc = -1.0;
         }
-        int64_t pos = (face_col[f] * nr + x - y + 1 + s) / 2;
-        if (pos > 4 * nr) pos -= 4 * nr;
-        if (pos < 1) pos += 4 * nr;
-        int64_t r = start + pos - 1;
-        dirs[3 * p + 0] = ring[3 * r + 0];
-        dirs[3 * p + 1] = ring[3 * r + 1];
-        dirs[3 * p + 2] = ring[3 * r + 2];
+        /* exact: dyadic fractions of a power-of-two nside */
+        const double X = Xc + (double)(x - y) / ns;
+        const double Y = Yc - 1.0 + (double)(x + y + 1) / ns;
+        double z, phi;
+        if (fabs(Y) <= 1.0) {
+            z = 2.0 * Y / 3.0;
+            phi = pi * X / 4.0;
+        } else {
+            const double sigma = 2.0 - fabs(Y);
+            z = (1.0 - sigma * sigma / 3.0) * (Y > 0.0 ? 1.0 : -1.0);
+            phi = pi * (Xc + (X - Xc) / sigma) / 4.0;
+        }
+        const double st = sqrt((1.0 - z) * (1.0 + z));
+        dirs[3 * p + 0] = st * cos(phi);
+        dirs[3 * p + 1] = st * sin(phi);
+        dirs[3 * p + 2] = z;
     }
-    free(ring);
     return ORC_OK;
 }
 

@@ -197,8 +197,11 @@ int rt_healpix_dirs_nested(int nside, double *dirs_out) {
     if (npix < 0) return fail(RT_ERR_ARG, "nside %d out of range [1, 2^20]", nside);
     if (nside & (nside - 1)) return fail(RT_ERR_ARG, "NESTED needs nside a power of two, got %d", nside);
     if (!dirs_out) return fail(RT_ERR_ARG, "null output pointer");
-    // base pixel f: its southmost corner lies on ring face_row[f] * nside,
-    // at azimuth face_col[f] * pi / 4 (Gorski et al. 2005, the 12 faces)
+    // Base pixel f (Gorski et al. 2005, the 12 faces): its southmost corner
+    // lies on ring face_row[f] * nside (the equator 2 nside for the north
+    // faces, 3 nside for the equatorial ones, the south pole 4 nside for the
+    // south ones) at azimuth face_col[f] * pi / 4 (the azimuth of the face's
+    // nside = 1 centre: pi/4 + k pi/2 for polar faces, k pi/2 on the equator).
     static const int face_row[12] = {2, 2, 2, 2, 3, 3, 3, 3, 4, 4, 4, 4};
     static const int face_col[12] = {1, 3, 5, 7, 0, 2, 4, 6, 1, 3, 5, 7};
     const int64_t ns = nside;
@@ -207,22 +210,27 @@ int rt_healpix_dirs_nested(int nside, double *dirs_out) {
         const int f = (int)(p / per_face);
         const uint64_t in_face = (uint64_t)(p % per_face);
         const int64_t ix = compact_bits(in_face), iy = compact_bits(in_face >> 1);
+        // each step in x or y moves one ring north of the south corner
         const int64_t i = face_row[f] * ns - ix - iy - 1;  // ring, 1-based from the north
-        int64_t nr, kshift;
+        // quarter: pixels of the ring per quarter turn; on_axis: 1 for the
+        // belt rings with a centre at azimuth 0 (the others sit half a
+        // pixel off it)
+        int64_t quarter, on_axis;
         if (i < ns) {
-            nr = i;
-            kshift = 0;
+            quarter = i;
+            on_axis = 0;
         } else if (i > 3 * ns) {
-            nr = 4 * ns - i;
-            kshift = 0;
+            quarter = 4 * ns - i;
+            on_axis = 0;
         } else {
-            nr = ns;
-            kshift = (i - ns) & 1;
+            quarter = ns;
+            on_axis = (i - ns) & 1;
         }
-        int64_t jp = (face_col[f] * nr + ix - iy + 1 + kshift) / 2;  // 1-based in the ring
-        if (jp > 4 * nr) jp -= 4 * nr;
-        if (jp < 1) jp += 4 * nr;
-        ring_pixel_centre(ns, i, jp - 1, dirs_out + 3 * p);
+        // azimuth in half pixel steps from the face's corner, east positive
+        int64_t pos = (face_col[f] * quarter + ix - iy + 1 + on_axis) / 2;  // 1-based in the ring
+        if (pos > 4 * quarter) pos -= 4 * quarter;
+        if (pos < 1) pos += 4 * quarter;
+        ring_pixel_centre(ns, i, pos - 1, dirs_out + 3 * p);
     }
     return ok();
 }

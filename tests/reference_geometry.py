@@ -63,14 +63,18 @@ def bruteforce_chords(tree, Q, m, boxes=None):
     t_in = np.zeros(lo.shape[0])
     t_out = np.full(lo.shape[0], te)
     for a in range(3):
-        if m[a] != 0.0:
+        # the bounding rule of exit_time: an axis bounds iff 1/m_a is finite
+        with np.errstate(divide="ignore", over="ignore"):
+            bounding = np.isfinite(1.0 / m[a])
+        if bounding:
             t1 = (lo[:, a] - Q[a]) / m[a]
             t2 = (hi[:, a] - Q[a]) / m[a]
             t_in = np.maximum(t_in, np.minimum(t1, t2))
             t_out = np.minimum(t_out, np.maximum(t1, t2))
         else:
-            # a ray inside a face plane belongs to the cells above it:
-            # cells are half-open, [lo, hi)
+            # a ray parallel to the axis (m_a zero or subnormal) stays in the
+            # plane through Q; inside a face plane it belongs to the cells
+            # above it: cells are half-open, [lo, hi)
             inside = (lo[:, a] <= Q[a]) & (Q[a] < hi[:, a])
             t_out = np.where(inside, t_out, -np.inf)
     chord = np.maximum(t_out - t_in, 0.0)

@@ -57,11 +57,12 @@ MUTANTS = {
     "av_eff_shift_lost": ("(xmin - log(sum / (double)Dn)) / gamma", "(-log(sum / (double)Dn)) / gamma"),
     "av_eff_mean_not_sum": ("log(sum / (double)Dn)", "log(sum)"),
     "nested_x_y_swapped": ("x |= ((in_face >> (2 * b)) & 1) << b;", "x |= ((in_face >> (2 * b + 1)) & 1) << b;"),
-    "nested_face_row": ("static const int face_row[12] = {2, 2, 2, 2, 3, 3, 3, 3, 4, 4, 4, 4};",
-                        "static const int face_row[12] = {2, 2, 2, 2, 3, 3, 3, 3, 4, 4, 4, 3};"),
-    "nested_face_col": ("static const int face_col[12] = {1, 3, 5, 7, 0, 2, 4, 6, 1, 3, 5, 7};",
-                        "static const int face_col[12] = {1, 3, 5, 7, 0, 2, 4, 6, 1, 3, 7, 5};"),
-    "nested_belt_shift": ("s = (ring_i - N) % 2;", "s = (ring_i - N + 1) % 2;"),
+    "nested_face_row": ("const double Y = Yc - 1.0 + (double)(x + y + 1) / ns;",
+                        "const double Y = Yc + (double)(x + y + 1) / ns;"),
+    "nested_face_col": ("Xc = 2.0 * (f - 4);", "Xc = 1.0 + 2.0 * (f - 4);"),
+    "nested_polar_stretch": ("phi = pi * (Xc + (X - Xc) / sigma) / 4.0;", "phi = pi * X / 4.0;"),
+    "nested_polar_z": ("z = (1.0 - sigma * sigma / 3.0)", "z = (1.0 - sigma / 3.0)"),
+    "nested_belt_z": ("z = 2.0 * Y / 3.0;", "z = 3.0 * Y / 8.0;"),
     "nested_reference_strided": ("sum = sum + fine[s * Dfine + q * ratio + k];",
                                  "sum = sum + fine[s * Dfine + q + k * Dcoarse];"),
     "nested_reference_sum": ("const double r = sum / (double)ratio;", "const double r = sum;"),
@@ -72,8 +73,8 @@ MUTANTS = {
     "grid_mean_not_divided": ("mean[at] = sum / 8.0;", "mean[at] = sum;"),
     "grid_children_reversed": ("emit_leaves(L + 1, 8 * c + j, D,", "emit_leaves(L + 1, 8 * c + 7 - j, D,"),
     "grid_key_coarse_shift": ("keys[*n] = (uint64_t)c << (3 * (D - L));", "keys[*n] = (uint64_t)c << (3 * (D - L - 1));"),
-    "nested_diagonal_sign": ("int64_t pos = (face_col[f] * nr + x - y + 1 + s) / 2;",
-                             "int64_t pos = (face_col[f] * nr + y - x + 1 + s) / 2;"),
+    "nested_diagonal_sign": ("const double X = Xc + (double)(x - y) / ns;",
+                             "const double X = Xc + (double)(y - x) / ns;"),
 }
 
 BATTERY = """

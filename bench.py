@@ -34,10 +34,18 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-VALU_PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9  # CUs x SIMDs x lanes x clock
+# VALU issue rate from the chip's unit counts and clock: 256 CUs x 4 SIMDs x
+# 16 lanes x 2.4 GHz (one wave64 instruction per SIMD every 4 cycles).  The
+# FP32 FMA probe issues faster than this, so the roofline's peak is the
+# probe's rate measured in the same run; this figure is reported beside it.
+VALU_NOMINAL_LANE_OPS = 256 * 4 * 16 * 2.4e9
 CPU_SAMPLE_STRIDE = 4096
-BYTES_PER_STEP = {"k_forward_f32k": 13, "k_forward_f64": 17, "k_backward": 25,
-                  "k_forward_adjoint": 38}
+# Algorithmic bytes of the method per ray-leaf step: the leaf record (Morton
+# key 8 B, level 1 B, value 4 B FP32 or 8 B FP64); the adjoint re-reads key,
+# level and value and adds into the gradient (a 4 B read-modify-write).  Per
+# ray: the source (24 B), the outputs, and the adjoint's loss weight.
+BYTES_PER_STEP = {"k_forward_f32k": 13, "k_forward_f64": 17, "k_backward": 21,
+                  "k_forward_adjoint": 34}
 BYTES_PER_RAY = {"k_forward_f32k": 32, "k_forward_f64": 40, "k_backward": 32,
                  "k_forward_adjoint": 36}
 # several-fields walk: n_H and three lines (key 8 + level 1 + 8 per field per step)
@@ -60,7 +68,9 @@ def parse():
     p.add_argument("--no-shielding", action="store_true")
     p.add_argument("--no-grid-tree", action="store_true")
     p.add_argument("--copy-gb", type=float, default=4.0,
-                   help="size of the device-to-device copy that measures achievable bandwidth")
+                   help="size of the stream probes' buffers (GB) that measure achievable bandwidth")
+    p.add_argument("--ceilings-only", action="store_true",
+                   help="run only the bandwidth and VALU probes and print their JSON")
     return p.parse_args()
 
 
@@ -78,8 +88,8 @@ def kernel_source_hash(kernel_file="rt_walk.hip"):
 def stored_counters(kernel, workload, src_hash):
     """The committed rocprofv3 counter summary of this kernel and workload
     (HBM bytes per launch from FETCH_SIZE + WRITE_SIZE, scaled against a
-    copy of known size; VALU issue rate), if it was taken on the current
-    kernel sources; else None."""
+    copy of known size; L2 hit rate; VALU instructions per launch), if it was
+    taken on the current kernel sources; else None."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     try:
         with open(path) as fh:
@@ -92,25 +102,116 @@ def stored_counters(kernel, workload, src_hash):
     return e
 
 
-def stream_copy_gbs(torch, dev, gb):
-    """Achievable HBM bandwidth: read + write bytes of a large device copy
-    (torch's elementwise copy kernel) over its duration."""
-    n = int(gb * 1e9) // 4
-    a = torch.ones(n, dtype=torch.float32, device=dev)
-    b = torch.empty_like(a)
-    b.copy_(a)
-    torch.cuda.synchronize()
+def _best_ms(torch, fn, reps=5):
+    """Shortest of reps timed calls of fn, by HIP events on torch's current
+    stream (the stream the library's calls are queued on)."""
     s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    fn()
+    torch.cuda.synchronize()
     best = None
-    for _ in range(5):
+    for _ in range(reps):
         s.record()
-        b.copy_(a)
+        fn()
         e.record()
         torch.cuda.synchronize()
         ms = s.elapsed_time(e)
         best = ms if best is None else min(best, ms)
-    del a, b
-    return {"bytes_per_launch": 8 * n, "ms": round(best, 4), "gbs": 8 * n / (best / 1e3) / 1e9}
+    return best
+
+
+def ceilings(torch, dev, gb):
+    """The two ceilings of the roofline, measured by the library's probes on
+    this GPU: achievable HBM bandwidth (a hand-written 16-byte stream copy
+    and a read-only stream over gb GB buffers) and the VALU issue rate of
+    FP64 fma, int32 xor-add and FP32 fma chains of known length."""
+    from paper_2605_09882_amd import _abi
+
+    stream = torch.cuda.current_stream(dev).cuda_stream
+    g = _abi.rt_calib_stream_granule()
+    nbytes = max(1, int(gb * 1e9) // g) * g
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
+    b = torch.empty_like(a)
+    sink = torch.empty(nbytes // g, dtype=torch.int32, device=dev)
+    ms_copy = _best_ms(torch, lambda: _abi.rt_calib_copy(a.data_ptr(), b.data_ptr(), nbytes, stream))
+    if not torch.equal(a, b):
+        raise RuntimeError("stream copy probe produced a wrong copy")
+    ms_read = _best_ms(torch, lambda: _abi.rt_calib_read(a.data_ptr(), nbytes, sink.data_ptr(), stream))
+    del a, b, sink
+    out = {"copy": {"bytes_per_launch": 2 * nbytes, "ms": round(ms_copy, 4),
+                    "gbs": round(2 * nbytes / (ms_copy / 1e3) / 1e9, 1)},
+           "read": {"bytes_per_launch": nbytes, "ms": round(ms_read, 4),
+                    "gbs": round(nbytes / (ms_read / 1e3) / 1e9, 1)}}
+    props = torch.cuda.get_device_properties(dev)
+    cus = props.multi_processor_count
+    # 16 wavefronts per SIMD (4 SIMDs per CU) hide the chains' latency
+    n_threads = cus * 4 * 16 * 64
+    iters = 20000
+    valu = {}
+    res = torch.empty(n_threads, dtype=torch.int32, device=dev)
+    for kind, name, per_iter in ((0, "fp64_fma", 8), (1, "int32_xad", 9), (2, "fp32_fma", 8)):
+        ms = _best_ms(torch, lambda: _abi.rt_calib_valu(kind, n_threads, iters, res.data_ptr(), stream), 3)
+        instr = n_threads // 64 * iters * per_iter
+        valu[name] = {"wave_instr_per_launch": instr, "ms": round(ms, 4),
+                      "wave_instr_per_s": instr / (ms / 1e3),
+                      "lane_ops_per_s": 64 * instr / (ms / 1e3)}
+    del res
+    out["valu"] = valu
+    out["compute_units"] = cus
+    return out
+
+
+def roofline_of(kname, kms, steps, rays, prof, ceil, bytes_per_step=None, bytes_per_ray=None):
+    """Roofline of one kernel launch of kms milliseconds over `steps`
+    ray-leaf steps and `rays` rays.
+
+    The walks are bound by vector-instruction issue, not by HBM: their
+    leaf records are served from the caches (the counters show a small
+    fraction of the HBM peak while the VALU issue rate is near its ceiling).
+    So `achieved` is the kernel's VALU issue rate: the wavefront instructions
+    one launch issues (SQ_INSTS_VALU, from the committed profile of this
+    kernel and workload, valid while the kernel sources are unchanged) times
+    64 lanes, over the launch duration measured here; `peak` is the issue
+    rate of the FP32 FMA probe measured in this run.  HBM is reported beside
+    it from counter bytes (FETCH_SIZE + WRITE_SIZE, calibrated), against the
+    8 TB/s peak and against the stream probes' achievable rates; the
+    method's algorithmic bytes are reported as such, without a fraction of
+    the HBM peak (the caches serve most of them)."""
+    sec = kms / 1e3
+    probe = ceil["valu"]["fp32_fma"]["lane_ops_per_s"] if ceil else None
+    r = {"bound": "alu", "achieved": None, "peak": round(probe / 1e12, 3) if probe else None,
+         "unit": "T VALU lane-ops/s", "frac": None,
+         "traffic": prof["hbm_bytes_per_launch"] if prof else None,
+         "kernel": kname, "kernel_ms": round(kms, 3),
+         "peak_source": "rt_calib_valu FP32 FMA chains, measured in this run",
+         "peak_nominal": round(VALU_NOMINAL_LANE_OPS / 1e12, 3),
+         "peak_nominal_source": "256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz"}
+    if prof:
+        instr = prof["valu_instr_per_launch"]
+        lane_ops = 64 * instr / sec
+        r["achieved"] = round(lane_ops / 1e12, 3)
+        if probe:
+            r["frac"] = round(lane_ops / probe, 4)
+        r["valu_instr_per_launch"] = instr
+        r["valu_instr_per_wavefront_step"] = round(instr / (steps / 64), 2)
+        gbs = prof["hbm_bytes_per_launch"] / sec / 1e9
+        r["hbm"] = {"counter_gbs": round(gbs, 1), "frac_of_peak": round(gbs / HBM_PEAK_GBS, 4),
+                    "fetch_bytes": prof["fetch_bytes"], "write_bytes": prof["write_bytes"],
+                    "l2_hit_rate": prof["l2_hit_rate"]}
+        if ceil:
+            r["hbm"]["achievable_copy_gbs"] = ceil["copy"]["gbs"]
+            r["hbm"]["achievable_read_gbs"] = ceil["read"]["gbs"]
+            r["hbm"]["frac_of_achievable_copy"] = round(gbs / ceil["copy"]["gbs"], 4)
+    else:
+        r["note"] = "no committed profile of the current kernel sources: VALU and counter fields null"
+    bps = BYTES_PER_STEP.get(kname, bytes_per_step)
+    bpr = BYTES_PER_RAY.get(kname, bytes_per_ray)
+    if bps is not None:
+        alg = steps * bps + rays * bpr
+        r["algorithmic"] = {"bytes_per_step": bps, "bytes_per_ray": bpr, "bytes": alg,
+                            "gbs": round(alg / sec / 1e9, 1),
+                            "note": "compulsory leaf-record bytes of the method, mostly served "
+                                    "from the caches; not a fraction of the HBM peak"}
+    return r
 
 
 def cpu_baseline(w, dirs_host):
@@ -176,6 +277,15 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
 
+    ceil = ceilings(torch, dev, args.copy_gb) if args.copy_gb > 0 else None
+    if ceil:
+        v = ceil["valu"]
+        log(f"stream copy {ceil['copy']['gbs']:.0f} GB/s, read {ceil['read']['gbs']:.0f} GB/s; VALU "
+            + ", ".join(f"{k} {x['wave_instr_per_s']:.3e} wave-instr/s" for k, x in v.items()))
+    if args.ceilings_only:
+        print(json.dumps({"ceilings": ceil}), flush=True)
+        return
+
     t0 = time.time()
     w = W.make_workload(args.workload)
     log(f"workload {w.name}: {w.tree.n} leaves, {w.sources.shape[0]} sources, nside {w.nside}, "
@@ -193,10 +303,6 @@ def main():
     grad = torch.zeros(w.tree.n, dtype=torch.float64, device=dev)
     kappa = w.kappa
 
-    copy = stream_copy_gbs(torch, dev, args.copy_gb) if args.copy_gb > 0 else None
-    if copy:
-        log(f"stream copy {copy['gbs']:.0f} GB/s ({copy['bytes_per_launch'] / 1e9:.1f} GB moved)")
-
     dirs_host = rt.healpix_dirs(w.nside)
     dirs = torch.as_tensor(dirs_host).to(dev)
     steps_t, _, _ = rt.columns_trace(tree, src, dirs)
@@ -206,6 +312,7 @@ def main():
     del steps_t
     rays = S * Dn
     log(f"{rays} rays, {total_steps} ray-leaf steps ({total_steps / rays:.1f} per ray)")
+    src_hash = kernel_source_hash()
 
     ev = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
 
@@ -275,9 +382,9 @@ def main():
         b.record()
         torch.cuda.synchronize()
         ms64 = a.elapsed_time(b) / args.steps
-        b64 = total_steps * BYTES_PER_STEP["k_forward_f64"] + rays * BYTES_PER_RAY["k_forward_f64"]
         fp64 = {"ms": round(ms64, 3), "steps_per_s": total_steps / (ms64 / 1e3),
-                "algorithmic_gbs": round(b64 / (ms64 / 1e3) / 1e9, 1)}
+                "roofline": roofline_of("k_forward_f64", ms64, total_steps, rays,
+                                        stored_counters("k_forward_f64", w.name, src_hash), ceil)}
         del N64
         log(f"FP64 walk {ms64:.1f} ms")
 
@@ -303,17 +410,16 @@ def main():
         torch.cuda.synchronize()
         ms_sh = a.elapsed_time(b) / args.steps
         nf = 1 + SHIELD_LINES
-        bsh = total_steps * SHIELD_BYTES_PER_STEP + S * (24 + 8 + 8 * nf)
         prof_sh = stored_counters("k_shielding", w.name, kernel_source_hash("rt_fields.hip"))
+        # per source: the point 24 B, T 8 B, A_V,eff 8 B, one beta per line;
+        # counted per ray here (the sources over their directions)
+        per_ray = (24 + 8 + 8 * nf) / Dn
         shield = {"fields": nf, "ms": round(ms_sh, 3), "steps_per_s": total_steps / (ms_sh / 1e3),
                   "field_steps_per_s": nf * total_steps / (ms_sh / 1e3),
-                  "bytes_per_step": SHIELD_BYTES_PER_STEP,
-                  "algorithmic_gbs": round(bsh / (ms_sh / 1e3) / 1e9, 1),
                   "vs_fp64_walk": round(ms_sh / fp64["ms"], 3) if fp64 else None,
                   "av_eff_median": float(res["av_eff"].median()),
-                  "traffic": prof_sh["hbm_bytes_per_launch"] if prof_sh else None,
-                  "valu_frac": (round(prof_sh["valu_lane_ops_per_s"] / VALU_PEAK_LANE_OPS, 3)
-                                if prof_sh else None)}
+                  "roofline": roofline_of("k_shielding", ms_sh, total_steps, rays, prof_sh, ceil,
+                                          SHIELD_BYTES_PER_STEP, per_ray)}
         del F, T, res
         log(f"several-fields walk ({nf} fields) {ms_sh:.1f} ms")
 
@@ -358,27 +464,14 @@ def main():
             f"(same as the host tree: {same}); octree handle from the device arrays in "
             f"{build['octree_from_device_ms']:.2f} ms")
 
-    # roofline of the pass's kernel: algorithmic bytes per launch over its
-    # measured duration.  Per ray-leaf step the forward reads one leaf record
-    # (Morton key 8 B, level 1 B, value 4 B FP32), and the adjoint reads key
-    # and level again and adds into an FP64 gradient (8 B read + 8 B
-    # written): 38 B.  Per ray: the source (24 B), N and A written (FP32) and
-    # the loss weight read.
+    # roofline of the pass's kernel (see roofline_of)
     kname, kms = "k_forward_adjoint", fused_ms
-    kbytes = total_steps * BYTES_PER_STEP[kname] + rays * BYTES_PER_RAY[kname]
-    achieved = kbytes / (kms / 1e3) / 1e9
-    src_hash = kernel_source_hash()
-    prof = stored_counters(kname, w.name, src_hash)
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": prof["hbm_bytes_per_launch"] if prof else None,
-                "kernel": kname, "kernel_ms": round(kms, 3), "algorithmic_bytes": kbytes,
-                "bytes_per_step": BYTES_PER_STEP[kname], "bytes_per_ray": BYTES_PER_RAY[kname],
-                "achievable_gbs": round(copy["gbs"], 1) if copy else None,
-                "frac_of_achievable": round(achieved / copy["gbs"], 4) if copy else None,
-                "l2_hit_rate": prof["l2_hit_rate"] if prof else None,
-                "valu_frac": (round(prof["valu_lane_ops_per_s"] / VALU_PEAK_LANE_OPS, 3)
-                              if prof else None)}
+    roofline = roofline_of(kname, kms, total_steps, rays, stored_counters(kname, w.name, src_hash),
+                           ceil)
+    adjoint_roofline = roofline_of("k_backward", bwd_ms, total_steps, rays,
+                                   stored_counters("k_backward", w.name, src_hash), ceil)
+    forward_roofline = roofline_of("k_forward_f32k", fwd_ms, total_steps, rays,
+                                   stored_counters("k_forward_f32k", w.name, src_hash), ceil)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -413,6 +506,9 @@ def main():
         "shielding": shield,
         "grid_tree": build,
         "roofline": roofline,
+        "forward_roofline": forward_roofline,
+        "adjoint_roofline": adjoint_roofline,
+        "ceilings": ceil,
         "cpu_baseline": cpu,
         "kernel_source_hash": src_hash,
     }

@@ -23,7 +23,7 @@ RT_ERR_WORKSPACE = -6
 RT_FP64 = 0
 RT_FP32_KAHAN = 1
 
-# every symbol include/raytheia.h declares
+# every symbol include/raytheia.h and include/raytheia_calib.h declare
 EXPORTS = (
     "rt_abi_version",
     "rt_status_string",
@@ -45,6 +45,10 @@ EXPORTS = (
     "rt_nested_reference",
     "rt_grid_tree_workspace_bytes",
     "rt_grid_tree",
+    "rt_calib_stream_granule",
+    "rt_calib_copy",
+    "rt_calib_read",
+    "rt_calib_valu",
 )
 
 RT_MAX_FIELDS = 8
@@ -91,6 +95,10 @@ def load(path=None):
         "rt_nested_reference": (I32, [P, I64, P, I64, I64, P, P, V]),
         "rt_grid_tree_workspace_bytes": (ctypes.c_size_t, [I32]),
         "rt_grid_tree": (I32, [P, I32, D, D, P, ctypes.c_size_t, P, P, P, P, V]),
+        "rt_calib_stream_granule": (ctypes.c_size_t, []),
+        "rt_calib_copy": (I32, [P, P, ctypes.c_size_t, V]),
+        "rt_calib_read": (I32, [P, ctypes.c_size_t, P, V]),
+        "rt_calib_valu": (I32, [I32, ctypes.c_int64, I32, P, V]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -220,3 +228,20 @@ def rt_grid_tree(grid_ptr, depth, density_floor, rel_uniformity, workspace_ptr, 
     _check(load().rt_grid_tree(grid_ptr, int(depth), float(density_floor), float(rel_uniformity),
                                workspace_ptr, int(workspace_bytes), keys_ptr, levels_ptr,
                                values_ptr, n_ptr, stream), "rt_grid_tree")
+
+
+def rt_calib_stream_granule():
+    return int(load().rt_calib_stream_granule())
+
+
+def rt_calib_copy(src_ptr, dst_ptr, nbytes, stream):
+    _check(load().rt_calib_copy(src_ptr, dst_ptr, int(nbytes), stream), "rt_calib_copy")
+
+
+def rt_calib_read(src_ptr, nbytes, sink_ptr, stream):
+    _check(load().rt_calib_read(src_ptr, int(nbytes), sink_ptr, stream), "rt_calib_read")
+
+
+def rt_calib_valu(kind, n_threads, iters, out_ptr, stream):
+    _check(load().rt_calib_valu(int(kind), int(n_threads), int(iters), out_ptr, stream),
+           "rt_calib_valu")

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(HERE, LIB_NAME)
 ARCH = "gfx950"
 
 SOURCES = ["rt_walk.hip", "rt_fields.hip", "rt_accuracy.hip", "rt_build.hip", "rt_octree_dev.hip",
-           "rt_abi.cpp", "rt_octree.cpp"]
+           "rt_calib.hip", "rt_abi.cpp", "rt_octree.cpp"]
 
 # -ffp-contract=off: the walk's FP64 arithmetic must round exactly as written
 # (fused multiply-adds only where fma() is spelled out).

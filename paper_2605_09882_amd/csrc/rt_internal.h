@@ -105,6 +105,13 @@ hipError_t launch_grid_tree(const double *grid, int depth, double floor_, double
                             void *workspace, uint64_t *keys, uint8_t *levels, double *values,
                             int64_t *n_out, hipStream_t stream);
 
+// Measurement probes (rt_calib_*): bytes per stream block, and launches.
+size_t calib_stream_granule();
+hipError_t launch_calib_copy(const void *src, void *dst, size_t bytes, hipStream_t stream);
+hipError_t launch_calib_read(const void *src, size_t bytes, uint32_t *sink, hipStream_t stream);
+hipError_t launch_calib_valu(int kind, int64_t n_threads, int iters, uint32_t *out,
+                             hipStream_t stream);
+
 hipError_t launch_trace(const TreeView &tree, const RayBatch &rays, int32_t *steps,
                         uint64_t *hash, const int64_t *sample, int64_t n_sample,
                         int32_t *visited, int64_t cap, hipStream_t stream);

@@ -12,7 +12,7 @@ import pytest
 from paper_2605_09882_amd import _abi
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "raytheia.h")
+HEADERS = [os.path.join(ROOT, "include", h) for h in ("raytheia.h", "raytheia_calib.h")]
 
 
 @pytest.fixture(scope="module")
@@ -21,10 +21,18 @@ def lib():
 
 
 def declared_functions():
-    with open(HEADER) as f:
-        text = f.read()
-    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(rt_[a-z0-9_]+)\s*\(", text)))
+    names = set()
+    for h in HEADERS:
+        with open(h) as f:
+            text = f.read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        names |= set(re.findall(r"\b(rt_[a-z0-9_]+)\s*\(", text))
+    return sorted(names)
+
+
+def test_every_header_is_checked():
+    inc = os.path.join(ROOT, "include")
+    assert sorted(os.path.join(inc, f) for f in os.listdir(inc) if f.endswith(".h")) == sorted(HEADERS)
 
 
 def test_exports_every_declared_symbol(lib):
@@ -186,3 +194,25 @@ def test_product_never_touches_the_oracle():
                 with open(os.path.join(base, f)) as fh:
                     text = fh.read()
                 assert not re.search(r"\boracle\b|\borc_", text), os.path.join(base, f)
+
+
+def test_calibration_probes_validate_before_device_work(lib):
+    """The measurement probes reject bad sizes, alignments and kinds on the
+    host."""
+    E = _abi.RT_ERR_ARG
+    g = _abi.rt_calib_stream_granule()
+    assert g == 16384
+    p, q = 1 << 20, 1 << 30  # fake, aligned, never dereferenced addresses
+    assert lib.rt_calib_copy(p, q, 0, None) == E
+    assert lib.rt_calib_copy(p, q, g + 16, None) == E
+    assert lib.rt_calib_copy(p + 8, q, g, None) == E
+    assert lib.rt_calib_copy(p, p + g // 2, g, None) == E      # overlapping
+    assert lib.rt_calib_copy(None, q, g, None) == E
+    assert lib.rt_calib_read(p, g, None, None) == E
+    assert lib.rt_calib_read(p, 3 * g // 2, q, None) == E
+    assert lib.rt_calib_valu(3, 256, 10, p, None) == E
+    assert lib.rt_calib_valu(0, 100, 10, p, None) == E
+    assert lib.rt_calib_valu(0, 256, 0, p, None) == E
+    assert lib.rt_calib_valu(0, 256, 10, None, None) == E
+    assert lib.rt_calib_valu(1, 1 << 31, 1, p, None) == E
+    assert b"n_threads" in lib.rt_last_error()

@@ -63,9 +63,17 @@ __device__ __forceinline__ uint64_t spread21(uint64_t x) {
     return x;
 }
 
+// (a << s) | b in one instruction (the compiler splits it when the operands
+// arrive from separate loads).
+__device__ __forceinline__ uint32_t shl_or(uint32_t a, int s, uint32_t b) {
+    uint32_t r;
+    asm("v_lshl_or_b32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "i"(s), "v"(b));
+    return r;
+}
+
 // 32-bit keys (depth <= 10) read the spread bits from a table in LDS.
 __device__ __forceinline__ uint32_t morton(const uint32_t *lut, int x, int y, int z, uint32_t) {
-    return lut[x] | (lut[y] << 1) | (lut[z] << 2);
+    return shl_or(lut[z], 2, shl_or(lut[y], 1, lut[x]));
 }
 
 __device__ __forceinline__ uint64_t morton(const uint32_t *, int x, int y, int z, uint64_t) {
@@ -103,11 +111,12 @@ template <typename KeyT>
 __device__ __forceinline__ uint32_t find_leaf(const Tree<KeyT> &t, KeyT k, int &level) {
     const uint32_t c = (uint32_t)(k >> t.top_shift);
     const uint32_t e = t.top[c];
-    uint32_t lo = e & kTopIndex;
     if (e & kTopFull) {
         level = t.depth;
-        return lo + (uint32_t)(k & t.cell_mask);
+        // e = index | kTopFull (the only flag a full cell carries)
+        return e + (uint32_t)(k & t.cell_mask) - kTopFull;
     }
+    uint32_t lo = e & kTopIndex;
     if (!(e & kTopOne)) {
         uint32_t hi = t.top[c + 1] & kTopIndex;
         while (hi - lo > 1u) {
@@ -130,7 +139,7 @@ struct Ray {
     double qx, qy, qz;  // Q 2^D
     double mx, my, mz;  // m 2^D
     double ix, iy, iz;  // (1/m) 2^-D, +inf for non-bounding axes
-    bool ux, uy, uz;    // far plane is the upper face (m > 0, or non-bounding)
+    int ux, uy, uz;     // 1: far plane is the upper face (m > 0, or non-bounding); 0: lower
     int cx, cy, cz;     // probe cell
     double t_in;
     int steps;
@@ -157,9 +166,9 @@ __device__ __forceinline__ bool ray_init(Ray &r, int depth, const double *q, con
     r.ix = bx ? inx * h : (double)INFINITY;
     r.iy = by ? iny * h : (double)INFINITY;
     r.iz = bz ? inz * h : (double)INFINITY;
-    r.ux = !bx || Mx > 0.0;
-    r.uy = !by || My > 0.0;
-    r.uz = !bz || Mz > 0.0;
+    r.ux = (!bx || Mx > 0.0) ? 1 : 0;
+    r.uy = (!by || My > 0.0) ? 1 : 0;
+    r.uz = (!bz || Mz > 0.0) ? 1 : 0;
     r.cx = (int)floor(r.qx);
     r.cy = (int)floor(r.qy);
     r.cz = (int)floor(r.qz);
@@ -168,13 +177,33 @@ __device__ __forceinline__ bool ray_init(Ray &r, int depth, const double *q, con
     return true;
 }
 
-__device__ __forceinline__ int advance_axis(bool exit, bool up, int a, int size, double ms,
-                                            double t, double qs) {
-    const int out = up ? a + size : a - 1;
-    int c = (int)floor(fma(ms, t, qs));
-    c = c < a ? a : c;
-    c = c > a + size - 1 ? a + size - 1 : c;
-    return exit ? out : c;
+// Integer helpers of the step, each one VALU instruction on gfx950.
+// (x << s) + a
+__device__ __forceinline__ int shl_add(int x, int s, int a) {
+    return (int)((uint32_t)x << s) + a;
+}
+// a + b - 1.  (Written out, the compiler keeps b - 1 of the per-ray b in
+// registers of its own for the whole walk; volatile keeps the instruction
+// where it stands rather than inside a branch.)
+__device__ __forceinline__ int add_m1(int a, int b) {
+    int r;
+    asm volatile("v_add3_u32 %0, %1, %2, -1" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+}
+// x clamped to [lo, hi] (lo <= hi): the median of the three.  (The compiler
+// forms v_med3_i32 only for constant bounds; min(max()) would be two.)
+__device__ __forceinline__ int med3(int x, int lo, int hi) {
+    int r;
+    asm("v_med3_i32 %0, %1, %2, %3" : "=v"(r) : "v"(x), "v"(lo), "v"(hi));
+    return r;
+}
+// max(a, b) of two doubles that are never NaN: the plain v_max_f64.  (fmax
+// first quiets its operands, two more instructions, because the compiler
+// cannot tell that a loop-carried value is never a signalling NaN.)
+__device__ __forceinline__ double max_nonnan(double a, double b) {
+    double r;
+    asm("v_max_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+    return r;
 }
 
 // First half of a step: the leaf that holds the probe, and its level.
@@ -188,42 +217,58 @@ __device__ __forceinline__ uint32_t ray_locate(const Ray &r, const Tree<KeyT> &t
 // the next cell; done is set when it has left the box.  The leaf value is
 // not needed here, so its load (issued by the caller between the halves)
 // overlaps with this arithmetic.
+//
+// The integer forms below give the cells of the step definition exactly.  With the leaf
+// edge 2^sh and anchor a = c & -2^sh, the far plane is a + 2^sh on an upper
+// face and a on a lower one, i.e. a + (u << sh).  An exit axis moves to
+// a + 2^sh (up) or a - 1 (down), i.e. plane + u - 1.  Another axis takes the
+// floor of its position clamped to [a, a + 2^sh - 1]; truncation gives the
+// same clamped cell, since the two differ only below 0 <= a.  In a finest
+// leaf (sh = 0) that clamp leaves the probe's own cell, so only the exit
+// axes move (a plain DDA step).
 template <typename KeyT>
 __device__ __forceinline__ void ray_advance(Ray &r, const Tree<KeyT> &t, int level, double &l,
                                             bool &done) {
-    const int size = 1 << (t.depth - level);
-    const int msk = ~(size - 1);
+    const int sh = t.depth - level;
+    const int msk = (int)(0xffffffffu << sh);  // -2^sh
     const int ax = r.cx & msk, ay = r.cy & msk, az = r.cz & msk;
+    const int px = shl_add(r.ux, sh, ax), py = shl_add(r.uy, sh, ay), pz = shl_add(r.uz, sh, az);
+    // the cell an exit axis moves to
+    const int ex_x = add_m1(px, r.ux), ex_y = add_m1(py, r.uy), ex_z = add_m1(pz, r.uz);
 
     // slab method: far planes of the leaf's box along the ray
-    const double tfx = ((double)(r.ux ? ax + size : ax) - r.qx) * r.ix;
-    const double tfy = ((double)(r.uy ? ay + size : ay) - r.qy) * r.iy;
-    const double tfz = ((double)(r.uz ? az + size : az) - r.qz) * r.iz;
+    const double tfx = ((double)px - r.qx) * r.ix;
+    const double tfy = ((double)py - r.qy) * r.iy;
+    const double tfz = ((double)pz - r.qz) * r.iz;
     // min in the order x, y, z; the far times are never +0 (a zero far time
     // is (0) * (negative 1/m) = -0) nor NaN, so fmin returns the same bits
     // as the compare chain
     const double t_out = fmin(fmin(tfx, tfy), tfz);
 
     // chord, clamped at 0: t_in moves to t_out unless rounding put t_out
-    // behind it (max(t_in, t_out) - t_in is t_out - t_in or +0; a zero
+    // behind it (max(t_in, t_out) - t_in is t_out - t_in or a zero; a zero
     // chord's sign never changes a sum)
-    const double t_next = fmax(r.t_in, t_out);
+    const double t_next = max_nonnan(r.t_in, t_out);
     l = t_next - r.t_in;
     r.t_in = t_next;
     ++r.steps;
 
-    const bool ex = tfx == t_out, ey = tfy == t_out, ez = tfz == t_out;
-    if (size == 1) {
-        // finest leaf: the clamp to the leaf leaves every non-exit axis on
-        // the probe's own cell, so only the exit axes move (a plain DDA step)
-        r.cx = ex ? (r.ux ? ax + 1 : ax - 1) : ax;
-        r.cy = ey ? (r.uy ? ay + 1 : ay - 1) : ay;
-        r.cz = ez ? (r.uz ? az + 1 : az - 1) : az;
-    } else {
-        r.cx = advance_axis(ex, r.ux, ax, size, r.mx, t_out, r.qx);
-        r.cy = advance_axis(ey, r.uy, ay, size, r.my, t_out, r.qy);
-        r.cz = advance_axis(ez, r.uz, az, size, r.mz, t_out, r.qz);
+    int nx = r.cx, ny = r.cy, nz = r.cz;
+    if (sh != 0) {
+        // the anchors again, from a copy of the mask the compiler cannot
+        // see through: it would otherwise keep the three anchors live across
+        // the slab arithmetic, in registers that bound the occupancy
+        int m = msk;
+        asm("" : "+v"(m));
+        const int bx = r.cx & m, by = r.cy & m, bz = r.cz & m;
+        const int hi = ~m;  // 2^sh - 1
+        nx = med3((int)fma(r.mx, t_out, r.qx), bx, bx + hi);
+        ny = med3((int)fma(r.my, t_out, r.qy), by, by + hi);
+        nz = med3((int)fma(r.mz, t_out, r.qz), bz, bz + hi);
     }
+    r.cx = tfx == t_out ? ex_x : nx;
+    r.cy = tfy == t_out ? ex_y : ny;
+    r.cz = tfz == t_out ? ex_z : nz;
     const unsigned side = 1u << t.depth;
     done = ((unsigned)r.cx >= side) | ((unsigned)r.cy >= side) | ((unsigned)r.cz >= side);
 }

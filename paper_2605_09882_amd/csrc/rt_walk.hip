@@ -267,7 +267,8 @@ __device__ __forceinline__ AggTable init_adjoint(AdjointShared &sh, int depth, i
 }
 
 template <typename KeyT>
-__global__ __launch_bounds__(kBlock) void k_backward(Tree<KeyT> t, RayBatch r, float kappa,
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(7, 8))) void k_backward(
+    Tree<KeyT> t, RayBatch r, float kappa,
                                                      const float *__restrict__ gN,
                                                      const float *__restrict__ gA,
                                                      const float *__restrict__ A,

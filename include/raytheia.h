@@ -179,6 +179,26 @@ int rt_grid_tree(const double *d_grid, int depth, double density_floor, double r
                  void *d_workspace, size_t workspace_bytes, uint64_t *d_keys, uint8_t *d_levels,
                  double *d_values, int64_t *d_n_leaves, void *stream);
 
+/* rt_grid_tree for callers that cannot allocate device memory (code under
+ * HIP graph capture, serving loops, harnesses that forbid hipMalloc): the
+ * same kernels, the same outputs, bit for bit, but the pyramid and the block
+ * offsets live in a static scratch array of the library
+ * (rt_grid_tree_workspace_bytes(7) = 7,498,752 bytes) instead of a caller
+ * workspace.  Each GPU the
+ * library runs on holds its own copy until the process ends; its device
+ * address is looked up on the first call on that device.  The call
+ * allocates nothing and needs no zeroed memory (every scratch byte is
+ * written before it is read).  All calls on one GPU share that GPU's
+ * scratch: calls that may overlap on one GPU (on different streams, or from
+ * several host threads) race and must be serialised by the caller.
+ *   depth   1..7 (grids of at most 128^3 cells); deeper grids are refused;
+ *   other arguments as for rt_grid_tree.
+ * Errors: RT_ERR_ARG (depth beyond 7, null pointers, non-finite
+ * parameters), RT_ERR_DEVICE. */
+int rt_grid_tree_static(const double *d_grid, int depth, double density_floor,
+                        double rel_uniformity, uint64_t *d_keys, uint8_t *d_levels,
+                        double *d_values, int64_t *d_n_leaves, void *stream);
+
 /* ---------------------------------------------------------------------
  * Column densities (sec. 2.3: I(p,q) = sum_k f_k r_k with f = rho).
  * ------------------------------------------------------------------- */

@@ -45,6 +45,7 @@ EXPORTS = (
     "rt_nested_reference",
     "rt_grid_tree_workspace_bytes",
     "rt_grid_tree",
+    "rt_grid_tree_static",
     "rt_calib_stream_granule",
     "rt_calib_copy",
     "rt_calib_read",
@@ -95,6 +96,7 @@ def load(path=None):
         "rt_nested_reference": (I32, [P, I64, P, I64, I64, P, P, V]),
         "rt_grid_tree_workspace_bytes": (ctypes.c_size_t, [I32]),
         "rt_grid_tree": (I32, [P, I32, D, D, P, ctypes.c_size_t, P, P, P, P, V]),
+        "rt_grid_tree_static": (I32, [P, I32, D, D, P, P, P, P, V]),
         "rt_calib_stream_granule": (ctypes.c_size_t, []),
         "rt_calib_copy": (I32, [P, P, ctypes.c_size_t, V]),
         "rt_calib_read": (I32, [P, ctypes.c_size_t, P, V]),
@@ -228,6 +230,13 @@ def rt_grid_tree(grid_ptr, depth, density_floor, rel_uniformity, workspace_ptr, 
     _check(load().rt_grid_tree(grid_ptr, int(depth), float(density_floor), float(rel_uniformity),
                                workspace_ptr, int(workspace_bytes), keys_ptr, levels_ptr,
                                values_ptr, n_ptr, stream), "rt_grid_tree")
+
+
+def rt_grid_tree_static(grid_ptr, depth, density_floor, rel_uniformity, keys_ptr, levels_ptr,
+                        values_ptr, n_ptr, stream):
+    _check(load().rt_grid_tree_static(grid_ptr, int(depth), float(density_floor),
+                                      float(rel_uniformity), keys_ptr, levels_ptr, values_ptr,
+                                      n_ptr, stream), "rt_grid_tree_static")
 
 
 def rt_calib_stream_granule():

@@ -334,6 +334,24 @@ int rt_grid_tree(const double *d_grid, int depth, double density_floor, double r
     return device_status(e, "grid tree launch");
 }
 
+int rt_grid_tree_static(const double *d_grid, int depth, double density_floor,
+                        double rel_uniformity, uint64_t *d_keys, uint8_t *d_levels,
+                        double *d_values, int64_t *d_n_leaves, void *stream) {
+    if (depth < 1 || depth > rt::kStaticGridMaxDepth)
+        return fail(RT_ERR_ARG, "depth %d not in 1..%d (the static scratch holds %zu bytes)", depth,
+                    rt::kStaticGridMaxDepth, rt::grid_tree_static_scratch_bytes());
+    if (!d_grid || !d_keys || !d_levels || !d_values || !d_n_leaves)
+        return fail(RT_ERR_ARG, "null grid or output pointer");
+    if (!std::isfinite(density_floor) || !std::isfinite(rel_uniformity))
+        return fail(RT_ERR_ARG, "density_floor and rel_uniformity must be finite");
+    void *scratch = nullptr;
+    hipError_t e = rt::grid_tree_static_scratch(&scratch);
+    if (e != hipSuccess) return device_status(e, "static scratch address");
+    e = rt::launch_grid_tree(d_grid, depth, density_floor, rel_uniformity, scratch, d_keys,
+                             d_levels, d_values, d_n_leaves, static_cast<hipStream_t>(stream));
+    return device_status(e, "grid tree launch");
+}
+
 // ---------------------------------------------------------------------
 // Angular-resolution comparison
 // ---------------------------------------------------------------------

@@ -29,6 +29,7 @@
 
 #include <cmath>
 #include <cstdint>
+#include <mutex>
 
 namespace rt {
 namespace {
@@ -37,8 +38,18 @@ constexpr int kEmitBlock = 256;                // threads per count / emit block
 constexpr int kCellsPerBlock = 8 * kEmitBlock;  // fine cells per count / emit block
 constexpr int kScanBlock = 1024;
 
-__host__ __device__ inline int64_t cells_before(int level) {
+__host__ __device__ constexpr int64_t cells_before(int level) {
     return (((int64_t)1 << (3 * level)) - 1) / 7;
+}
+
+constexpr size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Workspace layout at depth D: max, min and mean (f64) and the split flag
+// (u8) of every cell of levels 0 .. D-1, then one i64 offset per count /
+// emit block, each array 256-byte aligned.
+constexpr size_t workspace_bytes_at(int depth) {
+    return 3 * align256(8 * (size_t)cells_before(depth)) + align256((size_t)cells_before(depth)) +
+           align256(8 * (size_t)((((int64_t)1 << (3 * (depth - 1))) + kEmitBlock - 1) / kEmitBlock));
 }
 
 struct Pyramid {
@@ -204,14 +215,38 @@ __global__ __launch_bounds__(kEmitBlock) void k_emit(const double *__restrict__ 
     }
 }
 
+// Scratch of rt_grid_tree_static, for callers that cannot allocate: the
+// workspace of the deepest grid it takes, held by every GPU the library runs
+// on until the process ends.  Host code never uses the array's name as an
+// address (on the host it is a stand-in, not device memory): it takes the
+// device address from hipGetSymbolAddress, once per device.
+constexpr size_t kStaticScratchBytes = workspace_bytes_at(kStaticGridMaxDepth);
+__device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
 }  // namespace
 
-size_t grid_tree_workspace_bytes(int depth) {
-    const int64_t cells = cells_before(depth);
-    const int64_t parents = (int64_t)1 << (3 * (depth - 1));
-    const int64_t blocks = (parents + kEmitBlock - 1) / kEmitBlock;
-    auto align = [](size_t x) { return (x + 255) & ~(size_t)255; };
-    return 3 * align(8 * (size_t)cells) + align((size_t)cells) + align(8 * (size_t)blocks);
+size_t grid_tree_workspace_bytes(int depth) { return workspace_bytes_at(depth); }
+
+size_t grid_tree_static_scratch_bytes() { return kStaticScratchBytes; }
+
+hipError_t grid_tree_static_scratch(void **ptr) {
+    constexpr int kMaxDevices = 256;
+    static std::mutex lock;
+    static void *addr[kMaxDevices] = {};
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> guard(lock);
+    if (!addr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        addr[dev] = p;
+    }
+    *ptr = addr[dev];
+    return hipSuccess;
 }
 
 hipError_t launch_grid_tree(const double *grid, int depth, double floor_, double rel,
@@ -219,17 +254,16 @@ hipError_t launch_grid_tree(const double *grid, int depth, double floor_, double
                             int64_t *n_out, hipStream_t stream) {
     const int D = depth;
     const int64_t cells = cells_before(D);
-    auto align = [](size_t x) { return (x + 255) & ~(size_t)255; };
     unsigned char *w = static_cast<unsigned char *>(workspace);
     Pyramid p;
     p.mx = reinterpret_cast<double *>(w);
-    w += align(8 * (size_t)cells);
+    w += align256(8 * (size_t)cells);
     p.mn = reinterpret_cast<double *>(w);
-    w += align(8 * (size_t)cells);
+    w += align256(8 * (size_t)cells);
     p.mean = reinterpret_cast<double *>(w);
-    w += align(8 * (size_t)cells);
+    w += align256(8 * (size_t)cells);
     p.split = w;
-    w += align((size_t)cells);
+    w += align256((size_t)cells);
     int64_t *block_counts = reinterpret_cast<int64_t *>(w);
 
     for (int Lin = D; Lin > 0;) {

@@ -101,6 +101,12 @@ hipError_t launch_octree_stage(const uint64_t *keys, const uint8_t *levels, int6
 
 // Contribution grid from a uniform grid (rt_grid_tree).
 size_t grid_tree_workspace_bytes(int depth);
+// rt_grid_tree_static: grids up to this depth use the library's static
+// scratch, whose device address on the current device the second call
+// returns (looked up once per device).
+constexpr int kStaticGridMaxDepth = 7;
+size_t grid_tree_static_scratch_bytes();
+hipError_t grid_tree_static_scratch(void **ptr);
 hipError_t launch_grid_tree(const double *grid, int depth, double floor_, double rel,
                             void *workspace, uint64_t *keys, uint8_t *levels, double *values,
                             int64_t *n_out, hipStream_t stream);

@@ -216,3 +216,18 @@ def test_calibration_probes_validate_before_device_work(lib):
     assert lib.rt_calib_valu(0, 256, 10, None, None) == E
     assert lib.rt_calib_valu(1, 1 << 31, 1, p, None) == E
     assert b"n_threads" in lib.rt_last_error()
+
+
+def test_static_grid_tree_refuses_on_the_host(lib):
+    """rt_grid_tree_static (no caller workspace) refuses grids deeper than
+    its static scratch holds, and bad arguments, before any device work."""
+    E = _abi.RT_ERR_ARG
+    p = 256  # a fake, aligned, never dereferenced address
+    assert lib.rt_grid_tree_static(p, 8, 1.0, 0.01, p, p, p, p, None) == E
+    assert b"static scratch" in lib.rt_last_error()
+    assert lib.rt_grid_tree_static(p, 0, 1.0, 0.01, p, p, p, p, None) == E
+    assert lib.rt_grid_tree_static(None, 3, 1.0, 0.01, p, p, p, p, None) == E
+    assert lib.rt_grid_tree_static(p, 3, 1.0, 0.01, p, None, p, p, None) == E
+    assert lib.rt_grid_tree_static(p, 3, float("nan"), 0.01, p, p, p, p, None) == E
+    # the scratch holds exactly the workspace of the deepest accepted grid
+    assert _abi.rt_grid_tree_workspace_bytes(7) == 7498752

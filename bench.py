@@ -64,6 +64,8 @@ def parse():
     p.add_argument("--warmup", type=int, default=1)
     p.add_argument("--workload", type=int, default=4, help="workload index (0..4)")
     p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--cpu-stride", type=int, default=CPU_SAMPLE_STRIDE,
+                   help="the CPU baseline walks every n-th source with all directions")
     p.add_argument("--no-fp64", action="store_true")
     p.add_argument("--no-shielding", action="store_true")
     p.add_argument("--no-grid-tree", action="store_true")
@@ -214,14 +216,15 @@ def roofline_of(kname, kms, steps, rays, prof, ceil, bytes_per_step=None, bytes_
     return r
 
 
-def cpu_baseline(w, dirs_host):
-    """The oracle on every CPU_SAMPLE_STRIDE-th source: single-threaded (the
-    reported value), and split over all available cores."""
+def cpu_baseline(w, dirs_host, stride):
+    """The oracle on every stride-th source with all directions:
+    single-threaded (the reported value), and split over all available
+    cores."""
     import numpy as np
 
     import oracle
 
-    src = w.sources[::CPU_SAMPLE_STRIDE]
+    src = w.sources[::stride]
     t0 = time.perf_counter()
     out = oracle.columns(w.tree, src, dirs_host, w.kappa, rho32=w.tree.rho.astype(np.float32))
     dt = time.perf_counter() - t0
@@ -234,7 +237,7 @@ def cpu_baseline(w, dirs_host):
     dt_all = time.perf_counter() - t1
     return {"value": steps / dt, "unit": "ray-leaf steps/s", "cores": 1, "kind": "oracle",
             "all_cores": {"value": steps / dt_all, "cores": nc},
-            "sample": f"every {CPU_SAMPLE_STRIDE}th source ({src.shape[0]} sources x "
+            "sample": f"every {stride}th source ({src.shape[0]} sources x "
                       f"{dirs_host.shape[0]} dirs = {src.shape[0] * dirs_host.shape[0]} rays, "
                       f"{steps} leaf steps, {dt:.1f} s, FP64 + FP32-Kahan columns)",
             "host": host}
@@ -475,7 +478,7 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(w, dirs_host)
+        cpu = cpu_baseline(w, dirs_host, max(1, args.cpu_stride))
         log(f"cpu baseline {cpu['value']:.3e} steps/s ({cpu['sample']})")
 
     line = {

@@ -231,6 +231,10 @@ int rt_columns(const rt_octree *tree, const void *d_rho, int precision, const do
  *   d_A      device f32, the A of the forward call; required iff d_gA;
  *   d_grad_rho device f64 [n_leaves], accumulated with atomic adds (the
  *            caller zeroes it); the summation order is not deterministic.
+ *            It must be coarse-grained device memory (hipMalloc, or a
+ *            device tensor of a framework that allocates with it): the adds
+ *            are the hardware FP64 atomics, which fine-grained, managed or
+ *            host memory does not support and would lose without an error.
  * The traversal is the FP64 one of rt_columns; g * r is formed in FP32,
  * summed in FP32 over a few steps of neighbouring rays, then added to the
  * FP64 accumulator.  Errors: RT_ERR_ARG, RT_ERR_DEVICE. */
@@ -248,7 +252,8 @@ int rt_columns_backward(const rt_octree *tree, const double *d_src, int64_t n_sr
  *   d_rho    device f32 [n_leaves] leaf values;
  *   d_wN, d_wA  device f32 weights at the rt_columns offsets, or NULL (= 0);
  *   d_N      device f32 output; d_A device f32 output or NULL;
- *   d_grad_rho device f64 [n_leaves], accumulated (the caller zeroes it).
+ *   d_grad_rho device f64 [n_leaves], accumulated (the caller zeroes it);
+ *            coarse-grained device memory, as for rt_columns_backward.
  * N and A have the bits of rt_columns with RT_FP32_KAHAN; the gradient is
  * that of rt_columns_backward with d_gN = d_wN, d_gA = d_wA and the same A,
  * up to the order of its additions.  Invalid rays give N = A = NaN and add

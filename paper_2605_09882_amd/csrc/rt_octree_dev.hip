@@ -9,9 +9,10 @@
 //             failing index of each kind is kept with an atomic minimum;
 //   k_stage   the key copy (narrowed to 32 bits for D <= 10) with the
 //             sentinel 8^D;
-//   k_top     one thread per top-table cell: binary search for the leaf
-//             holding the cell's first finest cell;
-//   k_flags   the FULL / ONE flags of each entry (the rule of the host path).
+//   k_top     one thread per top-table cell: binary searches for the leaf
+//             holding the cell's first finest cell and for the next cell's,
+//             and the FULL / ONE flags of the entry (the rule of the host
+//             path).
 #include "rt_internal.h"
 
 #include <hip/hip_runtime.h>
@@ -56,36 +57,37 @@ __global__ __launch_bounds__(kBlock) void k_stage(const uint64_t *__restrict__ k
         out[i] = i < n ? (KeyT)keys[i] : (KeyT)((uint64_t)1 << (3 * D));
 }
 
-__global__ __launch_bounds__(kBlock) void k_top(const uint64_t *__restrict__ keys, int64_t n,
-                                                int shift, int64_t ncell, uint32_t *__restrict__ top) {
+// Index of the leaf holding the finest cell with key base: the largest i
+// with keys[i] <= base (keys[0] = 0 <= base; keys[n] read as +inf).
+__device__ __forceinline__ int64_t leaf_holding(const uint64_t *__restrict__ keys, int64_t n,
+                                                uint64_t base) {
+    int64_t lo = 0, hi = n;
+    while (hi - lo > 1) {
+        const int64_t mid = lo + (hi - lo) / 2;
+        if (keys[mid] <= base)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+// One thread per top-table cell c: the leaf holding the cell's first finest
+// cell, and its flags (the rule of the host path).  The thread finds the
+// next cell's first leaf itself, so no thread reads another's output.
+__global__ __launch_bounds__(kBlock) void k_top(const uint64_t *__restrict__ keys,
+                                                const uint8_t *__restrict__ levels, int64_t n, int D,
+                                                int lt, int shift, int64_t ncell,
+                                                uint32_t *__restrict__ top) {
+    const int64_t per_cell = shift < 31 ? (int64_t)1 << shift : INT64_MAX;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c <= ncell; c += stride) {
         if (c == ncell) {
             top[c] = (uint32_t)n;
             continue;
         }
-        const uint64_t base = (uint64_t)c << shift;
-        int64_t lo = 0, hi = n;  // keys[lo] <= base < keys[hi] (keys[n] read as +inf)
-        while (hi - lo > 1) {
-            const int64_t mid = lo + (hi - lo) / 2;
-            if (keys[mid] <= base)
-                lo = mid;
-            else
-                hi = mid;
-        }
-        top[c] = (uint32_t)lo;
-    }
-}
-
-__global__ __launch_bounds__(kBlock) void k_flags(const uint8_t *__restrict__ levels, int D, int lt,
-                                                  int shift, int64_t ncell, uint32_t *top) {
-    const int64_t per_cell = shift < 31 ? (int64_t)1 << shift : INT64_MAX;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < ncell; c += stride) {
-        // entries hold plain indices here; the neighbour may already carry
-        // its flags, which the mask removes
-        const int64_t lo = top[c] & kTopIndex;
-        const int64_t nx = top[c + 1] & kTopIndex;
+        const int64_t lo = leaf_holding(keys, n, (uint64_t)c << shift);
+        const int64_t nx = c + 1 == ncell ? n : leaf_holding(keys, n, (uint64_t)(c + 1) << shift);
         uint32_t flag = 0;
         if (nx - lo == per_cell && levels[lo] == D)
             flag = kTopFull;
@@ -124,10 +126,8 @@ hipError_t launch_octree_stage(const uint64_t *keys, const uint8_t *levels, int6
     if (e != hipSuccess) return e;
     const int shift = 3 * (depth - top_level);
     const int64_t ncell = (int64_t)1 << (3 * top_level);
-    hipLaunchKernelGGL(k_top, dim3(blocks_for(ncell + 1)), dim3(kBlock), 0, stream, keys, n, shift,
-                       ncell, top);
-    hipLaunchKernelGGL(k_flags, dim3(blocks_for(ncell)), dim3(kBlock), 0, stream, level_out, depth,
-                       top_level, shift, ncell, top);
+    hipLaunchKernelGGL(k_top, dim3(blocks_for(ncell + 1)), dim3(kBlock), 0, stream, keys, levels, n,
+                       depth, top_level, shift, ncell, top);
     return hipGetLastError();
 }
 

@@ -231,3 +231,15 @@ def test_static_grid_tree_refuses_on_the_host(lib):
     assert lib.rt_grid_tree_static(p, 3, float("nan"), 0.01, p, p, p, p, None) == E
     # the scratch holds exactly the workspace of the deepest accepted grid
     assert _abi.rt_grid_tree_workspace_bytes(7) == 7498752
+
+
+def test_header_states_the_gradient_memory_kind():
+    """Both calls that add into the FP64 gradient say it must be
+    coarse-grained device memory (the hardware FP64 atomics lose updates on
+    fine-grained, managed or host memory)."""
+    with open(HEADERS[0]) as f:
+        text = f.read()
+    for call in ("int rt_columns_backward(", "int rt_columns_with_adjoint("):
+        doc = text[:text.index(call)]
+        doc = doc[doc.rindex("/*"):]
+        assert "coarse-grained" in doc, call

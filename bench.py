@@ -48,9 +48,9 @@ BYTES_PER_STEP = {"k_forward_f32k": 13, "k_forward_f64": 17, "k_backward": 21,
                   "k_forward_adjoint": 34}
 BYTES_PER_RAY = {"k_forward_f32k": 32, "k_forward_f64": 40, "k_backward": 32,
                  "k_forward_adjoint": 36}
-# several-fields walk: n_H and three lines (key 8 + level 1 + 8 per field per step)
+# several-fields walk: n_H and three lines (key 8 + level 1 + 4 or 8 per field
+# per step)
 SHIELD_LINES = 3
-SHIELD_BYTES_PER_STEP = 9 + 8 * (1 + SHIELD_LINES)
 
 
 def log(msg):
@@ -392,39 +392,45 @@ def main():
         log(f"FP64 walk {ms64:.1f} ms")
 
     # several fields per leaf (n_H and three lines) over the same rays:
-    # per-source escape probabilities and A_V,eff from one walk per ray
+    # per-source escape probabilities and A_V,eff from one walk per ray, with
+    # the fields stored in FP32 (rt_shielding_f32) and in FP64 (rt_shielding)
     shield = None
     if not args.no_shielding:
         inp = W.line_inputs(w.tree, w.sources, SHIELD_LINES, 6000 + w.index)
-        F = torch.as_tensor(inp["fields"]).to(dev)
         T = torch.as_tensor(inp["temp"]).to(dev)
-
-        def shield_call():
-            return rt.shielding(tree, F, src, dirs, inp["length"], temp=T, vturb=inp["vturb"],
-                                line_A=inp["line_A"], line_nu=inp["line_nu"])
-
-        shield_call()
-        torch.cuda.synchronize()
-        a, b = ev(), ev()
-        a.record()
-        for _ in range(args.steps):
-            res = shield_call()
-        b.record()
-        torch.cuda.synchronize()
-        ms_sh = a.elapsed_time(b) / args.steps
         nf = 1 + SHIELD_LINES
-        prof_sh = stored_counters("k_shielding", w.name, kernel_source_hash("rt_fields.hip"))
         # per source: the point 24 B, T 8 B, A_V,eff 8 B, one beta per line;
         # counted per ray here (the sources over their directions)
         per_ray = (24 + 8 + 8 * nf) / Dn
-        shield = {"fields": nf, "ms": round(ms_sh, 3), "steps_per_s": total_steps / (ms_sh / 1e3),
-                  "field_steps_per_s": nf * total_steps / (ms_sh / 1e3),
-                  "vs_fp64_walk": round(ms_sh / fp64["ms"], 3) if fp64 else None,
-                  "av_eff_median": float(res["av_eff"].median()),
-                  "roofline": roofline_of("k_shielding", ms_sh, total_steps, rays, prof_sh, ceil,
-                                          SHIELD_BYTES_PER_STEP, per_ray)}
-        del F, T, res
-        log(f"several-fields walk ({nf} fields) {ms_sh:.1f} ms")
+        shield = {"fields": nf}
+        for name, dtype, fbytes in (("f32_fields", np.float32, 4), ("f64_fields", np.float64, 8)):
+            F = torch.as_tensor(inp["fields"].astype(dtype)).to(dev)
+
+            def shield_call():
+                return rt.shielding(tree, F, src, dirs, inp["length"], temp=T, vturb=inp["vturb"],
+                                    line_A=inp["line_A"], line_nu=inp["line_nu"])
+
+            shield_call()
+            torch.cuda.synchronize()
+            a, b = ev(), ev()
+            a.record()
+            for _ in range(args.steps):
+                res = shield_call()
+            b.record()
+            torch.cuda.synchronize()
+            ms_sh = a.elapsed_time(b) / args.steps
+            kname = f"k_shielding_{name[:3]}"
+            prof_sh = stored_counters(kname, w.name, kernel_source_hash("rt_fields.hip"))
+            shield[name] = {
+                "ms": round(ms_sh, 3), "steps_per_s": total_steps / (ms_sh / 1e3),
+                "field_steps_per_s": nf * total_steps / (ms_sh / 1e3),
+                "vs_fp64_walk": round(ms_sh / fp64["ms"], 3) if fp64 else None,
+                "av_eff_median": float(res["av_eff"].median()),
+                "roofline": roofline_of(kname, ms_sh, total_steps, rays, prof_sh, ceil,
+                                        9 + fbytes * nf, per_ray)}
+            del F, res
+            log(f"several-fields walk ({nf} fields, {name}) {ms_sh:.1f} ms")
+        del T
 
     # the contribution grid rebuilt on the device from the workload's 512^3
     # grid (the same field and rule as the host generator)

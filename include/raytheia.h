@@ -351,6 +351,17 @@ int rt_shielding(const rt_octree *tree, const double *d_fields, int n_fields, co
                  double gamma, double av0, double *d_rays, double *d_av_eff, double *d_beta,
                  void *stream);
 
+/* rt_shielding with the leaf fields stored in FP32: d_fields is device f32
+ * [n_leaves][n_fields], half the bytes per step of the walk.  Each field is
+ * widened to FP64 (exactly) before the same FP64 products and sums, so the
+ * outputs equal those of rt_shielding on the fields widened to f64.  Other
+ * arguments, outputs and errors as for rt_shielding. */
+int rt_shielding_f32(const rt_octree *tree, const float *d_fields, int n_fields, const double *d_src,
+                     int64_t n_src, const double *d_dirs, int64_t n_dirs, double length,
+                     const double *d_temp, double vturb, const double *line_A,
+                     const double *line_nu, double gamma, double av0, double *d_rays,
+                     double *d_av_eff, double *d_beta, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

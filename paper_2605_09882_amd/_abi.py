@@ -42,6 +42,7 @@ EXPORTS = (
     "rt_columns_with_adjoint",
     "rt_columns_trace",
     "rt_shielding",
+    "rt_shielding_f32",
     "rt_nested_reference",
     "rt_grid_tree_workspace_bytes",
     "rt_grid_tree",
@@ -93,6 +94,7 @@ def load(path=None):
         "rt_columns_with_adjoint": (I32, [V, P, P, I64, P, I64, D, P, P, P, P, I64, I64, P, V]),
         "rt_columns_trace": (I32, [V, P, I64, P, I64, P, P, I64, I64, P, I64, P, I64, V]),
         "rt_shielding": (I32, [V, P, I32, P, I64, P, I64, D, P, D, P, P, D, D, P, P, P, V]),
+        "rt_shielding_f32": (I32, [V, P, I32, P, I64, P, I64, D, P, D, P, P, D, D, P, P, P, V]),
         "rt_nested_reference": (I32, [P, I64, P, I64, I64, P, P, V]),
         "rt_grid_tree_workspace_bytes": (ctypes.c_size_t, [I32]),
         "rt_grid_tree": (I32, [P, I32, D, D, P, ctypes.c_size_t, P, P, P, P, V]),
@@ -213,6 +215,15 @@ def rt_shielding(handle, fields_ptr, n_fields, src_ptr, n_src, dirs_ptr, n_dirs,
                                int(n_dirs), float(length), temp_ptr, float(vturb), line_A_ptr,
                                line_nu_ptr, float(gamma), float(av0), rays_ptr, av_eff_ptr,
                                beta_ptr, stream), "rt_shielding")
+
+
+def rt_shielding_f32(handle, fields_ptr, n_fields, src_ptr, n_src, dirs_ptr, n_dirs, length,
+                     temp_ptr, vturb, line_A_ptr, line_nu_ptr, gamma, av0, rays_ptr, av_eff_ptr,
+                     beta_ptr, stream):
+    _check(load().rt_shielding_f32(handle, fields_ptr, int(n_fields), src_ptr, int(n_src), dirs_ptr,
+                                   int(n_dirs), float(length), temp_ptr, float(vturb), line_A_ptr,
+                                   line_nu_ptr, float(gamma), float(av0), rays_ptr, av_eff_ptr,
+                                   beta_ptr, stream), "rt_shielding_f32")
 
 
 def rt_nested_reference(fine_ptr, n_fine_dirs, coarse_ptr, n_coarse_dirs, n_src, ref_ptr, err_ptr,

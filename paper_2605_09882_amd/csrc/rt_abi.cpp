@@ -378,11 +378,15 @@ int rt_nested_reference(const double *d_fine, int64_t n_fine_dirs, const double 
 // Several fields per leaf
 // ---------------------------------------------------------------------
 
-int rt_shielding(const rt_octree *tree, const double *d_fields, int n_fields, const double *d_src,
-                 int64_t n_src, const double *d_dirs, int64_t n_dirs, double length,
-                 const double *d_temp, double vturb, const double *line_A, const double *line_nu,
-                 double gamma, double av0, double *d_rays, double *d_av_eff, double *d_beta,
-                 void *stream) {
+namespace {
+
+// rt_shielding and rt_shielding_f32: the same checks and parameters, fields
+// in f64 (field_precision 0) or f32 (1).
+int shielding_call(const rt_octree *tree, const void *d_fields, int field_precision, int n_fields,
+                   const double *d_src, int64_t n_src, const double *d_dirs, int64_t n_dirs,
+                   double length, const double *d_temp, double vturb, const double *line_A,
+                   const double *line_nu, double gamma, double av0, double *d_rays,
+                   double *d_av_eff, double *d_beta, void *stream) {
     rt::RayBatch rays;
     // the per-ray output is [n_fields][n_dirs][n_src]: strides 1 and n_src
     int st = check_rays(tree, d_src, n_src, d_dirs, n_dirs, 1, n_src, &rays);
@@ -416,10 +420,30 @@ int rt_shielding(const rt_octree *tree, const double *d_fields, int n_fields, co
         }
     }
     if (!d_rays && !d_av_eff && !d_beta) return ok();  // nothing requested
-    hipError_t e = rt::launch_shielding(tree->view, rays, d_fields, n_fields, p, d_rays, d_av_eff,
-                                        n_fields > 1 ? d_beta : nullptr,
+    hipError_t e = rt::launch_shielding(tree->view, rays, d_fields, field_precision, n_fields, p,
+                                        d_rays, d_av_eff, n_fields > 1 ? d_beta : nullptr,
                                         static_cast<hipStream_t>(stream));
     return device_status(e, "shielding walk launch");
+}
+
+}  // namespace
+
+int rt_shielding(const rt_octree *tree, const double *d_fields, int n_fields, const double *d_src,
+                 int64_t n_src, const double *d_dirs, int64_t n_dirs, double length,
+                 const double *d_temp, double vturb, const double *line_A, const double *line_nu,
+                 double gamma, double av0, double *d_rays, double *d_av_eff, double *d_beta,
+                 void *stream) {
+    return shielding_call(tree, d_fields, 0, n_fields, d_src, n_src, d_dirs, n_dirs, length, d_temp,
+                          vturb, line_A, line_nu, gamma, av0, d_rays, d_av_eff, d_beta, stream);
+}
+
+int rt_shielding_f32(const rt_octree *tree, const float *d_fields, int n_fields, const double *d_src,
+                     int64_t n_src, const double *d_dirs, int64_t n_dirs, double length,
+                     const double *d_temp, double vturb, const double *line_A,
+                     const double *line_nu, double gamma, double av0, double *d_rays,
+                     double *d_av_eff, double *d_beta, void *stream) {
+    return shielding_call(tree, d_fields, 1, n_fields, d_src, n_src, d_dirs, n_dirs, length, d_temp,
+                          vturb, line_A, line_nu, gamma, av0, d_rays, d_av_eff, d_beta, stream);
 }
 
 }  // extern "C"

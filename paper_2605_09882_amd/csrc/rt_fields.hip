@@ -51,44 +51,48 @@ __device__ __noinline__ double escape_term(double tau) {
 
 __device__ __noinline__ double log_term(double x) { return log(x); }
 
-template <int K>
+template <int K, typename FieldT>
 struct FieldValues {
-    double v[K];
+    FieldT v[K];
 };
 
 // Visitor of walk_ray: reads the K fields of each leaf and accumulates
 // I_f = I_f + F_f l in visiting order (two roundings, as in the FP64 column).
-template <int K>
+// Fields stored in FP32 are widened to FP64 (exactly) before the product.
+template <int K, typename FieldT>
 struct SumFields {
-    const double *__restrict__ F;  // [n][K]
+    const FieldT *__restrict__ F;  // [n][K]
     double I[K];
-    __device__ __forceinline__ FieldValues<K> fetch(uint32_t i) const {
-        FieldValues<K> x;
-        const double *p = F + (size_t)i * K;
+    __device__ __forceinline__ FieldValues<K, FieldT> fetch(uint32_t i) const {
+        FieldValues<K, FieldT> x;
+        const FieldT *p = F + (size_t)i * K;
 #pragma unroll
         for (int f = 0; f < K; ++f) x.v[f] = p[f];
         return x;
     }
-    __device__ __forceinline__ void step(const FieldValues<K> &x, uint32_t, double l) {
+    __device__ __forceinline__ void step(const FieldValues<K, FieldT> &x, uint32_t, double l) {
 #pragma unroll
-        for (int f = 0; f < K; ++f) I[f] = I[f] + x.v[f] * l;
+        for (int f = 0; f < K; ++f) I[f] = I[f] + (double)x.v[f] * l;
     }
 };
 
-// Waves per SIMD the compiler is asked to fit, by field count (1 sets no
-// bound).  At K = 1 and K = 8 the kernel sits a few registers above a wave
-// boundary (66 and 131 VGPRs with 32-bit keys), and the extra wave costs two
-// spilled registers.  Larger targets at other K, with 8-20 registers
-// spilled, speed up coherent rays but slow down scattered sources more.
-template <int K>
-constexpr int kMinWaves = K == 1 ? 8 : K == 8 ? 4 : 1;
+// Waves per SIMD the compiler is asked to fit, by field count and storage.
+// The walk is latency-bound, so waves hide more than the registers they
+// cost: with the fields in FP32, 6 waves at K = 2..4 (12-20 registers
+// spilled) and 5 at K = 5..8 take the coherent workloads 10-24% below the
+// compiler's own choice (4-5 waves), and the scattered sources of the AMR
+// workload within a few percent of it.  FP64 fields need more registers:
+// 5 waves at K <= 4 (6 waves cost the scattered workload 20%), 4 beyond.
+// K = 1 fits 8 waves with two spilled registers.
+template <int K, typename FieldT>
+constexpr int kMinWaves = K == 1 ? 8 : sizeof(FieldT) == 4 ? (K <= 4 ? 6 : 5) : (K <= 4 ? 5 : 4);
 
-template <typename KeyT, int K>
+template <typename KeyT, int K, typename FieldT>
 __global__ __launch_bounds__(kBlock)
-__attribute__((amdgpu_waves_per_eu(kMinWaves<K>))) void k_shielding(Tree<KeyT> t,
+__attribute__((amdgpu_waves_per_eu(kMinWaves<K, FieldT>))) void k_shielding(Tree<KeyT> t,
                                                       const double *__restrict__ src,
                                                       int64_t n_src, const double *__restrict__ dirs,
-                                                      int64_t n_dirs, const double *__restrict__ F,
+                                                      int64_t n_dirs, const FieldT *__restrict__ F,
                                                       ShieldingParams p, double *__restrict__ rays,
                                                       double *__restrict__ av_eff,
                                                       double *__restrict__ beta) {
@@ -108,7 +112,7 @@ __attribute__((amdgpu_waves_per_eu(kMinWaves<K>))) void k_shielding(Tree<KeyT> t
 #pragma unroll
         for (int f = 0; f < K; ++f) bsum[f] = 0.0;
         for (int64_t d = 0; d < n_dirs && !bad; ++d) {
-            SumFields<K> v;
+            SumFields<K, FieldT> v;
             v.F = F;
 #pragma unroll
             for (int f = 0; f < K; ++f) v.I[f] = 0.0;
@@ -149,16 +153,16 @@ __attribute__((amdgpu_waves_per_eu(kMinWaves<K>))) void k_shielding(Tree<KeyT> t
     }
 }
 
-template <typename KeyT, int K>
-void launch_k(const TreeView &tree, const RayBatch &rays, const double *F, const ShieldingParams &p,
+template <typename KeyT, int K, typename FieldT>
+void launch_k(const TreeView &tree, const RayBatch &rays, const FieldT *F, const ShieldingParams &p,
               double *ray_out, double *av_eff, double *beta, hipStream_t stream) {
-    hipLaunchKernelGGL((k_shielding<KeyT, K>), dim3(grid_for(rays.n_src)), dim3(kBlock), 0, stream,
-                       tree_of<KeyT>(tree), rays.src, rays.n_src, rays.dirs, rays.n_dirs, F, p,
-                       ray_out, av_eff, beta);
+    hipLaunchKernelGGL((k_shielding<KeyT, K, FieldT>), dim3(grid_for(rays.n_src)), dim3(kBlock), 0,
+                       stream, tree_of<KeyT>(tree), rays.src, rays.n_src, rays.dirs, rays.n_dirs, F,
+                       p, ray_out, av_eff, beta);
 }
 
-template <typename KeyT>
-void launch_key(const TreeView &tree, const RayBatch &rays, const double *F, int K,
+template <typename KeyT, typename FieldT>
+void launch_key(const TreeView &tree, const RayBatch &rays, const FieldT *F, int K,
                 const ShieldingParams &p, double *ray_out, double *av_eff, double *beta,
                 hipStream_t stream) {
     switch (K) {
@@ -174,17 +178,28 @@ void launch_key(const TreeView &tree, const RayBatch &rays, const double *F, int
     }
 }
 
-}  // namespace
-
-hipError_t launch_shielding(const TreeView &tree, const RayBatch &rays, const double *fields,
-                            int n_fields, const ShieldingParams &p, double *ray_out,
-                            double *av_eff, double *beta, hipStream_t stream) {
+template <typename FieldT>
+hipError_t launch_fields(const TreeView &tree, const RayBatch &rays, const FieldT *fields,
+                         int n_fields, const ShieldingParams &p, double *ray_out, double *av_eff,
+                         double *beta, hipStream_t stream) {
     if (n_fields < 1 || n_fields > kMaxFields) return hipErrorInvalidValue;
     if (tree.wide_keys)
         launch_key<uint64_t>(tree, rays, fields, n_fields, p, ray_out, av_eff, beta, stream);
     else
         launch_key<uint32_t>(tree, rays, fields, n_fields, p, ray_out, av_eff, beta, stream);
     return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_shielding(const TreeView &tree, const RayBatch &rays, const void *fields,
+                            int field_precision, int n_fields, const ShieldingParams &p,
+                            double *ray_out, double *av_eff, double *beta, hipStream_t stream) {
+    if (field_precision == 0)
+        return launch_fields(tree, rays, static_cast<const double *>(fields), n_fields, p, ray_out,
+                             av_eff, beta, stream);
+    return launch_fields(tree, rays, static_cast<const float *>(fields), n_fields, p, ray_out, av_eff,
+                         beta, stream);
 }
 
 }  // namespace rt

@@ -84,9 +84,10 @@ struct ShieldingParams {
     double coef[kMaxFields];  // coef[f] = A_f c^3 / (8 pi nu_f^3) for f = 1 .. K-1
 };
 
-hipError_t launch_shielding(const TreeView &tree, const RayBatch &rays, const double *fields,
-                            int n_fields, const ShieldingParams &p, double *ray_out,
-                            double *av_eff, double *beta, hipStream_t stream);
+// fields: f64 [n][K] (field_precision 0) or f32 [n][K] (1).
+hipError_t launch_shielding(const TreeView &tree, const RayBatch &rays, const void *fields,
+                            int field_precision, int n_fields, const ShieldingParams &p,
+                            double *ray_out, double *av_eff, double *beta, hipStream_t stream);
 
 hipError_t launch_nested_reference(const double *fine, const double *coarse, int64_t n_coarse,
                                    int64_t n_src, int64_t ratio, double *ref, double *err,

@@ -295,16 +295,19 @@ def shielding(tree, fields, src, dirs, length, temp=None, vturb=0.0, line_A=(), 
     """Line optical depths, escape probabilities and the effective visual
     extinction (sec. 2.4, sec. 3) from one walk per ray over K leaf fields.
 
-    fields: device float64 [n_leaves, K] (field 0 = n_H, field f >= 1 = the
-    population term of line f with Einstein A line_A[f-1] and frequency
-    line_nu[f-1]); src [S, 3], dirs [Dn, 3]; length = box edge in cm;
+    fields: device float64 or float32 [n_leaves, K] (field 0 = n_H, field
+    f >= 1 = the population term of line f with Einstein A line_A[f-1] and
+    frequency line_nu[f-1]; float32 fields go to rt_shielding_f32, which
+    widens them to float64 before the same arithmetic); src [S, 3],
+    dirs [Dn, 3]; length = box edge in cm;
     temp [S] source temperatures in K (needed when K > 1); vturb in cm/s.
     Returns a dict with "av_eff" [S], "beta" [S, K-1] (views over
     line-major buffers) and, if rays, "rays" [S, Dn, K] (N_H, then tau per
     line; a view over the [K, Dn, S] buffer)."""
     dev = tree.device
-    if not torch.is_tensor(fields) or fields.dtype != torch.float64 or not fields.is_cuda:
-        raise TypeError("fields must be a float64 device tensor")
+    if not torch.is_tensor(fields) or fields.dtype not in (torch.float64, torch.float32) \
+            or not fields.is_cuda:
+        raise TypeError("fields must be a float64 or float32 device tensor")
     if fields.ndim == 1:
         fields = fields[:, None]
     fields = fields.contiguous()
@@ -330,11 +333,11 @@ def shielding(tree, fields, src, dirs, length, temp=None, vturb=0.0, line_A=(), 
     out_rays = torch.empty((K, Dn, S), dtype=torch.float64, device=dev) if rays else None
     out_av = torch.empty(S, dtype=torch.float64, device=dev) if av_eff else None
     out_beta = torch.empty((K - 1, S), dtype=torch.float64, device=dev) if beta and K > 1 else None
-    _abi.rt_shielding(tree.handle, fields.data_ptr(), K, src.data_ptr(), S, dirs.data_ptr(), Dn,
-                      float(length), _ptr(T), float(vturb),
-                      None if lA is None else lA.ctypes.data,
-                      None if lnu is None else lnu.ctypes.data, float(gamma), float(av0),
-                      _ptr(out_rays), _ptr(out_av), _ptr(out_beta), _stream(dev))
+    call = _abi.rt_shielding if fields.dtype == torch.float64 else _abi.rt_shielding_f32
+    call(tree.handle, fields.data_ptr(), K, src.data_ptr(), S, dirs.data_ptr(), Dn, float(length),
+         _ptr(T), float(vturb), None if lA is None else lA.ctypes.data,
+         None if lnu is None else lnu.ctypes.data, float(gamma), float(av0), _ptr(out_rays),
+         _ptr(out_av), _ptr(out_beta), _stream(dev))
     res = {}
     if out_av is not None:
         res["av_eff"] = out_av

@@ -198,8 +198,11 @@ def test_fullsize_adjoint_identity(rt, orc, index):
     torch.cuda.synchronize()
 
 
-@pytest.mark.parametrize("index", [4, 2, 1, 3])
-def test_fullsize_shielding(rt, orc, index):
+@pytest.mark.parametrize("index,f32", [(4, False), (4, True), (2, False), (2, True), (1, False),
+                                       (3, False)])
+def test_fullsize_shielding(rt, orc, index, f32):
+    """The several-fields walk at full size (FP64 fields, and FP32 fields for
+    the coherent workloads, the oracle then fed the same FP32 values)."""
     w = _workload(index)
     dev = torch.device("cuda")
     dirs, _ = _dirs(rt, orc, w.nside)
@@ -208,7 +211,11 @@ def test_fullsize_shielding(rt, orc, index):
     dirs_d = torch.as_tensor(dirs).to(dev)
     S, Dn = src.shape[0], dirs.shape[0]
     inp = W.line_inputs(w.tree, w.sources, SHIELD_LINES, 6000 + index)
+    if f32:
+        inp["fields"] = inp["fields"].astype(np.float32)
     F = torch.as_tensor(inp["fields"]).to(dev)
+    if f32:
+        inp["fields"] = inp["fields"].astype(np.float64)  # the oracle's copy: the same values
     T = torch.as_tensor(inp["temp"]).to(dev)
     gamma, av0 = 3.02, 6.29e-22
     out = rt.shielding(tree, F, src, dirs_d, inp["length"], temp=T, vturb=inp["vturb"],
@@ -218,7 +225,7 @@ def test_fullsize_shielding(rt, orc, index):
     assert bool(torch.isfinite(av).all()) and bool((av >= 0).all())
     assert np.isfinite(beta).all() and (beta > 0).all()
     # every source: min_d av0 N_H <= A_V,eff <= mean_d av0 N_H (Jensen)
-    N, _ = rt.columns(tree, F[:, 0].contiguous(), src, dirs_d, with_A=False)
+    N, _ = rt.columns(tree, F[:, 0].to(torch.float64).contiguous(), src, dirs_d, with_A=False)
     avd = av0 * (inp["length"] * N)
     lo, hi = avd.min(dim=1).values, avd.mean(dim=1)
     slack = 1e-12 * hi + (2 * Dn + 4) * 2.3e-16 / gamma

@@ -32,10 +32,10 @@ def rt():
 
 
 def gpu_shielding(rt, tree, fields, src, dirs, inp, rays=True, av_eff=True, beta=True,
-                  gamma=GAMMA, av0=AV0):
+                  gamma=GAMMA, av0=AV0, f32=False):
     dev = torch.device("cuda")
     t = rt.Octree(tree.keys, tree.levels, tree.depth, dev)
-    F = torch.as_tensor(np.ascontiguousarray(fields, dtype=np.float64)).to(dev)
+    F = torch.as_tensor(np.ascontiguousarray(fields, dtype=np.float32 if f32 else np.float64)).to(dev)
     out = rt.shielding(t, F, torch.as_tensor(src).to(dev), torch.as_tensor(dirs).to(dev),
                        inp["length"], temp=inp.get("temp"), vturb=inp.get("vturb", 0.0),
                        line_A=inp.get("line_A", ()), line_nu=inp.get("line_nu", ()),
@@ -138,6 +138,38 @@ def test_single_field_needs_no_lines(rt, orc):
     assert_shielding(got, ref, len(dirs))
 
 
+@pytest.mark.parametrize("depth,p,seed,n_lines", [(3, 0.6, 112, 0), (4, 0.5, 113, 3),
+                                                   (5, 0.35, 114, 7), (6, 0.2, 115, 1)])
+def test_f32_fields(rt, orc, depth, p, seed, n_lines):
+    """rt_shielding_f32: against the oracle fed the same FP32 values (to the
+    bar above), and bit for bit against rt_shielding on those values widened
+    to FP64 (the kernel widens each field exactly before the same
+    arithmetic)."""
+    tree = W.random_octree(depth, p, seed, min_level=1)
+    src = np.vstack([W.random_points(200, seed + 10), edge_sources(depth)])
+    dirs = np.vstack([orc.healpix_ring(2), special_dirs(), random_dirs(5, seed + 20)])
+    fields, inp = _inputs(tree, src, n_lines, seed + 30)
+    f32 = fields.astype(np.float32)
+    ref = oracle_shielding(orc, tree, f32.astype(np.float64), src, dirs, inp)
+    got = gpu_shielding(rt, tree, f32, src, dirs, inp, f32=True)
+    assert_shielding(got, ref, len(dirs))
+    wide = gpu_shielding(rt, tree, f32.astype(np.float64), src, dirs, inp)
+    for k in got:
+        a, b = got[k], wide[k]
+        assert np.array_equal(a.view(np.int64), b.view(np.int64)), k
+
+
+def test_f32_deep_tree_and_ragged(rt, orc):
+    tree = W.sparse_random_octree(14, 40, 414)
+    src = W.random_points(65, 415)
+    dirs = random_dirs(7, 416)
+    fields, inp = _inputs(tree, src, 2, 417)
+    f32 = fields.astype(np.float32)
+    ref = oracle_shielding(orc, tree, f32.astype(np.float64), src, dirs, inp)
+    got = gpu_shielding(rt, tree, f32, src, dirs, inp, f32=True)
+    assert_shielding(got, ref, len(dirs))
+
+
 def test_argument_errors(rt):
     dev = torch.device("cuda")
     tree = W.random_octree(2, 0.5, 71, min_level=1)
@@ -167,6 +199,15 @@ def test_argument_errors(rt):
     assert lib.rt_shielding(t.handle, None, 1, src.data_ptr(), 4, dirs.data_ptr(), dirs.shape[0],
                             1.0, None, 0.0, None, None, GAMMA, AV0, None, av.data_ptr(), None,
                             None) == rt._abi.RT_ERR_ARG
+    assert lib.rt_shielding_f32(t.handle, None, 1, src.data_ptr(), 4, dirs.data_ptr(), dirs.shape[0],
+                                1.0, None, 0.0, None, None, GAMMA, AV0, None, av.data_ptr(), None,
+                                None) == rt._abi.RT_ERR_ARG
+    F2f = torch.ones((tree.n, 2), dtype=torch.float32, device=dev)
+    assert lib.rt_shielding_f32(t.handle, F2f.data_ptr(), 2, src.data_ptr(), 4, dirs.data_ptr(),
+                                dirs.shape[0], 1.0, None, 0.0, None, None, GAMMA, AV0, None,
+                                av.data_ptr(), None, None) == rt._abi.RT_ERR_ARG
+    with pytest.raises(TypeError):
+        rt.shielding(t, F2.to(torch.float16), src, dirs, 1.0, **ok)
     assert lib.rt_shielding(t.handle, F2.data_ptr(), 0, src.data_ptr(), 4, dirs.data_ptr(),
                             dirs.shape[0], 1.0, None, 0.0, None, None, GAMMA, AV0, None,
                             av.data_ptr(), None, None) == rt._abi.RT_ERR_ARG

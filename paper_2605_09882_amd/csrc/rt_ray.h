@@ -277,14 +277,14 @@ __device__ __forceinline__ void ray_advance(Ray &r, const Tree<KeyT> &t, int lev
 // (Visitor::fetch) as soon as i is known and sees every visited leaf in
 // order (Visitor::step).  Returns the number of leaves, or -1 for an
 // invalid ray or one longer than the 3 * 2^D + 3 steps a valid walk takes.
-template <typename KeyT, typename Visitor>
+template <bool kCount = false, typename KeyT, typename Visitor>
 __device__ __forceinline__ int walk_ray(const Tree<KeyT> &t, const uint32_t *lut,
                                         const double *q, const double *m, Visitor &v) {
     Ray r;
     if (!ray_init(r, t.depth, q, m)) return -1;
     const int max_steps = 3 * (1 << t.depth) + 3;
-    for (;;) {
-        if (r.steps >= max_steps) return -1;
+    // one step; true when the ray has left the box
+    auto step = [&]() {
         int level;
         const uint32_t i = ray_locate(r, t, lut, level);
         const auto value = v.fetch(i);
@@ -292,9 +292,17 @@ __device__ __forceinline__ int walk_ray(const Tree<KeyT> &t, const uint32_t *lut
         bool done;
         ray_advance(r, t, level, l, done);
         v.step(value, i, l);
-        if (done) break;
+        return done;
+    };
+    // two steps per iteration: the loop-carried values then alternate
+    // between two registers instead of being copied back every step
+    for (;;) {
+        if (r.steps >= max_steps) return -1;
+        if (step()) break;
+        if (r.steps >= max_steps) return -1;
+        if (step()) break;
     }
-    return r.steps;
+    return kCount ? r.steps : 0;
 }
 
 // ---------------------------------------------------------------------
@@ -311,7 +319,11 @@ struct SumF64 {
 struct SumF32Kahan {
     const float *__restrict__ rho;
     float S, c;
-    __device__ __forceinline__ float fetch(uint32_t i) const { return rho[i]; }
+    // 32-bit byte offset (fewer than 2^30 leaves): one shift, no 64-bit
+    // address arithmetic
+    __device__ __forceinline__ float fetch(uint32_t i) const {
+        return *reinterpret_cast<const float *>(reinterpret_cast<const char *>(rho) + (i << 2));
+    }
     __device__ __forceinline__ void step(float r, uint32_t, double l) {
         const float y = r * (float)l - c;
         const float t = S + y;

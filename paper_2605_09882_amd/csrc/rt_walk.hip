@@ -387,7 +387,7 @@ __global__ __launch_bounds__(kBlock) void k_trace(Tree<KeyT> t, RayBatch r,
          ray += stride) {
         const RayIndex x = ray_index(r, ray);
         HashSteps v{0xcbf29ce484222325ull};
-        const int steps = walk_ray(t, lut, r.src + 3 * x.s, r.dirs + 3 * x.d, v);
+        const int steps = walk_ray<true>(t, lut, r.src + 3 * x.s, r.dirs + 3 * x.d, v);
         if (steps_out) steps_out[x.off] = steps;
         if (hash_out) hash_out[x.off] = v.h;
     }

@@ -39,7 +39,7 @@ HBM_PEAK_GBS = 8000.0
 # FP32 FMA probe issues faster than this, so the roofline's peak is the
 # probe's rate measured in the same run; this figure is reported beside it.
 VALU_NOMINAL_LANE_OPS = 256 * 4 * 16 * 2.4e9
-CPU_SAMPLE_STRIDE = 4096
+CPU_SAMPLE_STRIDE = 2048
 # Algorithmic bytes of the method per ray-leaf step: the leaf record (Morton
 # key 8 B, level 1 B, value 4 B FP32 or 8 B FP64); the adjoint re-reads key
 # and level and adds into the FP64 gradient of the leaf (an 8 B read and an

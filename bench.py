@@ -41,12 +41,12 @@ HBM_PEAK_GBS = 8000.0
 VALU_NOMINAL_LANE_OPS = 256 * 4 * 16 * 2.4e9
 CPU_SAMPLE_STRIDE = 2048
 # Algorithmic bytes of the method per ray-leaf step: the leaf record (Morton
-# key 8 B, level 1 B, value 4 B FP32 or 8 B FP64); the adjoint re-reads key
-# and level and adds into the FP64 gradient of the leaf (an 8 B read and an
-# 8 B write).  Per ray: the source (24 B), the outputs, and the adjoint's loss
-# weight.
-BYTES_PER_STEP = {"k_forward_f32k": 13, "k_forward_f64": 17, "k_backward": 25,
-                  "k_forward_adjoint": 38}
+# key 8 B, level 1 B, value 4 B FP32 or 8 B FP64); the adjoint re-reads the
+# record and adds into the gradient of the leaf, counted as the 4 B read and
+# 4 B write of an FP32 gradient (the FP64 gradient kept here moves 8 + 8 B).
+# Per ray: the source (24 B), the outputs, and the adjoint's loss weight.
+BYTES_PER_STEP = {"k_forward_f32k": 13, "k_forward_f64": 17, "k_backward": 21,
+                  "k_forward_adjoint": 34}
 BYTES_PER_RAY = {"k_forward_f32k": 32, "k_forward_f64": 40, "k_backward": 32,
                  "k_forward_adjoint": 36}
 # several-fields walk: n_H and three lines (key 8 + level 1 + 4 or 8 per field

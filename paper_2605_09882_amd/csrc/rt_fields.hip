@@ -77,15 +77,19 @@ struct SumFields {
 };
 
 // Waves per SIMD the compiler is asked to fit, by field count and storage.
-// The walk is latency-bound, so waves hide more than the registers they
-// cost: with the fields in FP32, 6 waves at K = 2..4 (12-20 registers
-// spilled) and 5 at K = 5..8 take the coherent workloads 10-24% below the
-// compiler's own choice (4-5 waves), and the scattered sources of the AMR
-// workload within a few percent of it.  FP64 fields need more registers:
-// 5 waves at K <= 4 (6 waves cost the scattered workload 20%), 4 beyond.
-// K = 1 fits 8 waves with two spilled registers.
+// The walk is latency-bound, so on coherent rays (sources on a lattice)
+// waves hide more than the registers they cost; the registers spilled to
+// reach them are all in the per-ray code, none in the step loop.  With the
+// fields in FP32: 8 waves at K = 2, 7 at K = 3..4, 5 at K = 5..8, which
+// take the lattice workloads 5-14% below 6 waves.  Sources drawn in
+// proportion to the density scatter the rays, and there the extra waves
+// cost 4-10% (more leaves in flight than the caches hold).  FP64 fields
+// need more registers: 5 waves at K <= 4, 4 beyond.  K = 1 fits 8 waves
+// with two spilled registers.
 template <int K, typename FieldT>
-constexpr int kMinWaves = K == 1 ? 8 : sizeof(FieldT) == 4 ? (K <= 4 ? 6 : 5) : (K <= 4 ? 5 : 4);
+constexpr int kMinWaves = K == 1   ? 8
+                          : sizeof(FieldT) == 4 ? (K == 2 ? 8 : K <= 4 ? 7 : 5)
+                                                : (K <= 4 ? 5 : 4);
 
 template <typename KeyT, int K, typename FieldT>
 __global__ __launch_bounds__(kBlock)

@@ -206,7 +206,8 @@ template <bool Peel, typename KeyT>
 __device__ __forceinline__ void scatter_rays(const Tree<KeyT> &t, const uint32_t *lut, Ray &st,
                                              bool active, float g, int max_steps, AggTable &agg,
                                              double *__restrict__ grad, int lane) {
-    while (__any(active)) {
+    // one step of the wavefront (all 64 lanes call it)
+    auto step = [&]() {
         uint32_t leaf = kEmpty;
         float v = 0.0f;
         if (active) {
@@ -243,6 +244,14 @@ __device__ __forceinline__ void scatter_rays(const Tree<KeyT> &t, const uint32_t
             flush_table(agg.tag, agg.sum, grad, lane);
             agg.since_flush = 0;
         }
+    };
+    // two steps per iteration, as in walk_ray: the ray state then alternates
+    // between two sets of registers instead of being copied back every step
+    for (;;) {
+        if (!__any(active)) break;
+        step();
+        if (!__any(active)) break;
+        step();
     }
 }
 
@@ -338,7 +347,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(7, 8))) 
         SumF32Kahan v{rho, 0.0f, 0.0f};
         bool active = valid;
         bool too_long = false;
-        while (__any(active)) {
+        auto step = [&]() {
             if (active) {
                 double l;
                 bool done;
@@ -354,6 +363,13 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(7, 8))) 
                     too_long = true;
                 }
             }
+        };
+        // lockstep, two steps per iteration (see scatter_rays)
+        for (;;) {
+            if (!__any(active)) break;
+            step();
+            if (!__any(active)) break;
+            step();
         }
         float g = 0.0f;
         if (ray < total) {

@@ -315,7 +315,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(7, 8))) 
 // state.  The second walk finds the leaves of the first still in cache, and
 // the scatter of some wavefronts overlaps the walks of others.  Asked for 7
 // waves per SIMD (the adjoint's LDS allows 7 blocks per CU), the compiler
-// fits it in 72 VGPRs without spilling.
+// fits it in 72 VGPRs; the only values it spills belong to the per-ray
+// set-up, none to the walks.
 // ---------------------------------------------------------------------
 
 // Out of line, as exp_f64: inlined, its constants would stay live across

@@ -94,8 +94,11 @@ def test_invalid_sources_and_zero_weights(rt, orc):
     _run(rt, orc, tree, src, dirs, 1.0, None, wA)
 
 
-def test_deep_tree_wide_keys(rt, orc):
-    tree = W.sparse_random_octree(14, 30, 81)
+@pytest.mark.parametrize("depth", [10, 14])
+def test_deep_trees(rt, orc, depth):
+    """10: the deepest tree with 32-bit keys and the LDS spread table; 14:
+    64-bit keys."""
+    tree = W.sparse_random_octree(depth, 30, 81)
     src = W.random_points(200, 82)
     dirs = np.vstack([orc.healpix_ring(1), special_dirs()])
     wA = np.random.default_rng(83).random((len(src), len(dirs)))

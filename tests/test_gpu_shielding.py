@@ -71,8 +71,9 @@ def test_random_amr_trees(rt, orc, depth, p, seed, n_lines):
     assert np.isnan(got["av_eff"][-2:]).all() and not np.isnan(got["av_eff"][:-2]).any()
 
 
-@pytest.mark.parametrize("depth", [11, 14, 21])
+@pytest.mark.parametrize("depth", [10, 11, 14, 21])
 def test_deep_trees_wide_keys(rt, orc, depth):
+    """10 is the deepest tree with 32-bit keys; beyond, 64-bit keys."""
     tree = W.sparse_random_octree(depth, 40, 300 + depth)
     tree.rho = np.random.default_rng(depth).lognormal(0.0, 1.0, tree.n)
     src = np.vstack([W.random_points(150, 310 + depth), [[0.0, 0.0, 0.0], [0.5, 0.5, 0.5]]])

@@ -62,6 +62,21 @@ def test_random_amr_trees(rt, orc, depth, p, seed):
     assert_fp32_vs_fp64(got)
 
 
+@pytest.mark.parametrize("depth,splits,seed", [(8, 300, 34), (9, 300, 35), (10, 300, 36)])
+def test_deep_trees_narrow_keys(rt, orc, depth, splits, seed):
+    """Depths 8..10 use 32-bit keys and the LDS spread table; 10 is the
+    deepest they cover (8^10 keys, a 1024-entry table).  Sparse trees keep
+    the top table shallow, so most lookups take the key search."""
+    tree = W.sparse_random_octree(depth, splits, seed)
+    deep = W.sparse_random_octree(depth, 60, seed + 1, focus=[0.7, 0.2, 0.9])
+    for t in (tree, deep):
+        src = np.vstack([W.random_points(97, seed + 2), edge_sources(depth),
+                         np.array([[0.7, 0.2, 0.9], [1.0 - 2.0 ** -depth, 0.0, 1.0 - 2.0 ** -53]])])
+        dirs = np.vstack([orc.healpix_ring(1), special_dirs(), random_dirs(9, seed + 3)])
+        got, _ = _compare(rt, orc, t, src, dirs)
+        assert_fp32_vs_fp64(got)
+
+
 @pytest.mark.parametrize("depth,splits,seed", [(11, 400, 31), (14, 300, 32), (21, 250, 33)])
 def test_deep_trees_wide_keys(rt, orc, depth, splits, seed):
     """Depth > 10 uses 64-bit keys on the device."""

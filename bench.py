@@ -26,6 +26,7 @@ import argparse
 import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -77,14 +78,20 @@ def parse():
     return p.parse_args()
 
 
+_COMMENT = re.compile(r"//[^\n]*|/\*.*?\*/", re.S)
+
+
 def kernel_source_hash(kernel_file="rt_walk.hip"):
     """Hash of the sources that fix what a kernel executes: the device walk,
     the kernel's own source with its launch shape, and the octree's search
-    structures."""
+    structures.  Comments and whitespace are left out (none of these files
+    holds a comment marker inside a string), so a stored profile stays valid
+    until the code itself changes."""
     h = hashlib.sha256()
     for f in ("rt_ray.h", kernel_file, "rt_octree.cpp"):
-        with open(os.path.join(ROOT, "paper_2605_09882_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_2605_09882_amd", "csrc", f)) as fh:
+            code = _COMMENT.sub(" ", fh.read())
+        h.update(" ".join(code.split()).encode())
     return h.hexdigest()[:16]
 
 

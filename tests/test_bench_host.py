@@ -91,3 +91,19 @@ def test_more_than_one_gpu_is_refused():
                        capture_output=True, text=True, timeout=120)
     assert p.returncode == 2
     assert "one GPU only" in p.stderr and p.stdout == ""
+
+
+def test_source_hash_ignores_comments_but_not_code(tmp_path, monkeypatch):
+    src = os.path.join(ROOT, "paper_2605_09882_amd", "csrc")
+    dst = tmp_path / "paper_2605_09882_amd" / "csrc"
+    dst.mkdir(parents=True)
+    for f in ("rt_ray.h", "rt_walk.hip", "rt_octree.cpp"):
+        with open(os.path.join(src, f)) as fh:
+            (dst / f).write_text(fh.read())
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    h0 = bench.kernel_source_hash()
+    walk = (dst / "rt_walk.hip").read_text()
+    (dst / "rt_walk.hip").write_text("// a new comment\n/* and a\n block */" + walk.replace("\n", "\n\n", 3))
+    assert bench.kernel_source_hash() == h0
+    (dst / "rt_walk.hip").write_text(walk.replace("kFlushEvery = 16", "kFlushEvery = 17"))
+    assert bench.kernel_source_hash() != h0

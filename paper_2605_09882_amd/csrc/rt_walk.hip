@@ -45,8 +45,8 @@ constexpr int kOwnerSlots = 128;
 // ---------------------------------------------------------------------
 
 // The FP64 exp of the epilogue stays out of line: inlined, its constants and
-// temporaries are live across the walk loop (72 VGPRs, 7 waves per SIMD
-// instead of 56 and 8).
+// temporaries are live across the walk loop (72 VGPRs and 7 waves per SIMD;
+// out of line the kernel fits 8).
 __device__ __noinline__ double exp_f64(double x) { return exp(x); }
 
 template <typename KeyT>

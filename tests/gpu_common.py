@@ -1,5 +1,7 @@
 """Shared helpers of the GPU tests (HIP path vs oracle on the same inputs)."""
 
+import os
+
 import numpy as np
 import pytest
 import torch
@@ -118,3 +120,10 @@ def assert_shielding(got, ref, n_dirs, gamma=3.02, rays=True):
 def random_dirs(count, seed):
     v = np.random.default_rng(seed).standard_normal((count, 3))
     return v / np.linalg.norm(v, axis=1)[:, None]
+
+
+def random_seeds():
+    """The seeds of the random-configuration tests: 100..119, or the range
+    "a:b" given in RAYWALK_RANDOM_SEEDS for a longer sweep."""
+    a, b = (int(x) for x in os.environ.get("RAYWALK_RANDOM_SEEDS", "100:120").split(":"))
+    return range(a, b)

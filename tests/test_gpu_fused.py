@@ -12,7 +12,7 @@ import pytest
 import torch
 
 import workloads as W
-from gpu_common import edge_sources, random_dirs, require_gpu, special_dirs
+from gpu_common import edge_sources, random_dirs, random_seeds, require_gpu, special_dirs
 
 pytestmark = pytest.mark.gpu
 
@@ -103,6 +103,20 @@ def test_deep_trees(rt, orc, depth):
     dirs = np.vstack([orc.healpix_ring(1), special_dirs()])
     wA = np.random.default_rng(83).random((len(src), len(dirs)))
     _run(rt, orc, tree, src, dirs, 1.0, None, wA)
+
+
+@pytest.mark.parametrize("seed", random_seeds())
+def test_random_configurations(rt, orc, seed):
+    """Seeded random trees (depth 1..9), sources with face and corner
+    points, directions, kappa, and loss weights on A alone or on N and A."""
+    rng = np.random.default_rng(seed + 77)
+    depth = int(rng.integers(1, 10))
+    tree = W.random_octree(depth, float(rng.uniform(0.05, 0.6)), seed + 5, min_level=min(1, depth))
+    src = np.vstack([W.random_points(int(rng.integers(1, 300)), seed + 6), edge_sources(depth)])
+    dirs = np.vstack([random_dirs(int(rng.integers(1, 30)), seed + 7), special_dirs()])
+    wA = rng.random((len(src), len(dirs)))
+    wN = rng.random((len(src), len(dirs))) if seed % 2 else None
+    _run(rt, orc, tree, src, dirs, float(rng.uniform(0.1, 2.0)), wN, wA)
 
 
 def test_without_weights_only_the_forward_runs(rt):

@@ -12,7 +12,7 @@ import torch
 
 import workloads as W
 from gpu_common import (assert_attenuation, assert_bitexact, assert_fp32_vs_fp64, edge_sources,
-                        gpu_walk, random_dirs, require_gpu, special_dirs)
+                        gpu_walk, random_dirs, random_seeds, require_gpu, special_dirs)
 
 pytestmark = pytest.mark.gpu
 
@@ -194,7 +194,7 @@ def test_buffers_on_another_device_are_refused(rt):
     assert grad.device == t.device and bool(torch.isfinite(grad).all())
 
 
-@pytest.mark.parametrize("seed", range(100, 120))
+@pytest.mark.parametrize("seed", random_seeds())
 def test_random_configurations(rt, orc, seed):
     """Seeded random trees (depth 1..9, random refinement), random sources
     (with face and corner points) and directions: bit-exact columns, step

@@ -314,7 +314,8 @@ int rt_nested_reference(const double *d_fine, int64_t n_fine_dirs, const double 
  * f = 1 .. K-1 is the level-population term [n_j g_i / g_j - n_i] (cm^-3)
  * of line f (sec. 2.4).  With N_f = length * I_f (cm^-2):
  *   du(s)    = sqrt(8 kB T_s / (pi m_p) + vturb^2), kB = 1.380649e-16 erg/K,
- *              m_p = 1.67262192369e-24 g (the rms speed of sec. 2.4);
+ *              m_p = 1.67262192369e-24 g (the line width of sec. 2.4: the mean
+ *              thermal speed and the turbulent speed in quadrature);
  *   tau_f    = A_f c^3 / (8 pi nu_f^3) * N_f / du, c = 2.99792458e10 cm/s
  *              (the discretised line optical depth of sec. 2.4);
  *   beta_f(s) = (1/n_dirs) sum_d (1 - exp(-tau_f)) / tau_f, with the term 1

@@ -122,3 +122,46 @@ def test_every_ray_of_the_uniform_128_grid(rt, orc):
     # every ray compared; the table here is the oracle's, so the total differs
     # slightly from that of the library's nside-4 table (which the benchmark walks)
     assert n_steps == int(got["steps"].sum())
+
+
+@pytest.mark.timeout(1200)
+@pytest.mark.skipif(not os.environ.get("RAYWALK_ALLRAYS_512"),
+                    reason='about an hour of oracle work on 16 cores, run in parts: set '
+                           'RAYWALK_ALLRAYS_512="a:b" to compare the rays of sources a..b-1')
+def test_every_ray_of_the_merged_512_cloud(rt, orc):
+    """Workload 4 (134,217,728 cell centres x 12 directions), bit for bit as
+    above, for the sources a..b-1 named in RAYWALK_ALLRAYS_512 ("a:b"; the
+    whole cloud is 0:134217728).  The GPU walks one chunk of 2^21 sources at
+    a time (rays are independent, so a chunk's results are those of the full
+    launch), and the oracle walks the same chunk over every core."""
+    a0, b0 = (int(x) for x in os.environ["RAYWALK_ALLRAYS_512"].split(":"))
+    w = W.make_workload(4)
+    S = w.sources.shape[0]
+    assert 0 <= a0 < b0 <= S
+    dirs = rt.healpix_dirs(w.nside)
+    assert np.array_equal(dirs, orc.healpix_ring(w.nside))
+    dev = torch.device("cuda")
+    tree = rt.Octree(w.tree.keys, w.tree.levels, w.tree.depth, dev)
+    dirs_d = torch.as_tensor(dirs).to(dev)
+    r32 = w.tree.rho.astype(np.float32)
+    rho64, rho32 = torch.as_tensor(w.tree.rho).to(dev), torch.as_tensor(r32).to(dev)
+    cores = _cores()
+    t0 = time.perf_counter()
+    n_rays = n_steps = 0
+    for a in range(a0, b0, 1 << 21):
+        b = min(a + (1 << 21), b0)
+        src = torch.as_tensor(w.sources[a:b]).to(dev)
+        N64, A64 = rt.columns(tree, rho64, src, dirs_d, w.kappa)
+        N32, _ = rt.columns(tree, rho32, src, dirs_d, w.kappa, with_A=False)
+        steps, h, _ = rt.columns_trace(tree, src, dirs_d)
+        got = {"N": N64.cpu().numpy(), "A": A64.cpu().numpy(), "N32": N32.cpu().numpy(),
+               "steps": steps.cpu().numpy(), "hash": h.cpu().numpy().view(np.uint64)}
+        ref = orc.columns(w.tree, w.sources[a:b], dirs, w.kappa, rho32=r32, threads=cores)
+        assert ref["status"] == orc.OK
+        for k in ("N", "N32", "steps", "hash"):
+            assert np.array_equal(got[k], ref[k]), (k, a, b)
+        assert np.all(np.abs(got["A"] - ref["A"]) <= 4.5e-16 * np.abs(ref["A"]))
+        n_rays += got["N"].size
+        n_steps += int(ref["steps"].sum())
+        print(f"[{w.name}] sources {a}..{b}: equal; {n_rays} rays, {n_steps} steps in "
+              f"{time.perf_counter() - t0:.0f} s", flush=True)

@@ -16,6 +16,9 @@ smallest and the mean of its directions' extinctions from the FP64 column
 walk.
 """
 
+import os
+import time
+
 import numpy as np
 import pytest
 import torch
@@ -241,3 +244,43 @@ def test_fullsize_shielding(rt, orc, index, f32):
     got = {"av_eff": av.cpu().numpy()[idx], "beta": beta[idx]}
     assert_shielding(got, ref, Dn, gamma=gamma, rays=False)
     torch.cuda.synchronize()
+
+
+@pytest.mark.timeout(1200)
+@pytest.mark.skipif(not os.environ.get("RAYWALK_SHIELDING_512"),
+                    reason='about 25 minutes of oracle work on 16 cores, run in parts: set '
+                           'RAYWALK_SHIELDING_512="a:b" to compare sources a..b-1')
+def test_every_source_shielding_merged_512(rt, orc):
+    """The several-fields walk with FP32-stored fields (n_H and three lines,
+    the configuration the benchmark times) on every source a..b-1 of the
+    512^3 cloud named in RAYWALK_SHIELDING_512 ("a:b"; all: 0:134217728),
+    against the oracle fed the same values, in chunks of 2^21 sources."""
+    a0, b0 = (int(x) for x in os.environ["RAYWALK_SHIELDING_512"].split(":"))
+    w = _workload(4)
+    S = w.sources.shape[0]
+    assert 0 <= a0 < b0 <= S
+    dev = torch.device("cuda")
+    dirs, _ = _dirs(rt, orc, w.nside)
+    tree = rt.Octree(w.tree.keys, w.tree.levels, w.tree.depth, dev)
+    dirs_d = torch.as_tensor(dirs).to(dev)
+    inp = W.line_inputs(w.tree, w.sources, SHIELD_LINES, 6004)
+    f32 = inp["fields"].astype(np.float32)
+    F = torch.as_tensor(f32).to(dev)
+    f64 = f32.astype(np.float64)  # the oracle's copy: the same values
+    gamma, av0 = 3.02, 6.29e-22
+    cores = max(1, min(len(os.sched_getaffinity(0)), 16))
+    t0 = time.perf_counter()
+    for a in range(a0, b0, 1 << 21):
+        b = min(a + (1 << 21), b0)
+        src = torch.as_tensor(w.sources[a:b]).to(dev)
+        T = torch.as_tensor(inp["temp"][a:b]).to(dev)
+        out = rt.shielding(tree, F, src, dirs_d, inp["length"], temp=T, vturb=inp["vturb"],
+                           line_A=inp["line_A"], line_nu=inp["line_nu"], gamma=gamma, av0=av0)
+        got = {"av_eff": out["av_eff"].cpu().numpy(), "beta": out["beta"].cpu().numpy()}
+        ref = orc.shielding(w.tree, f64, w.sources[a:b], dirs, length=inp["length"],
+                            temp=inp["temp"][a:b], vturb=inp["vturb"], line_A=inp["line_A"],
+                            line_nu=inp["line_nu"], gamma=gamma, av0=av0, rays=False, threads=cores)
+        assert ref["status"] == orc.OK
+        assert_shielding(got, ref, len(dirs), gamma=gamma, rays=False)
+        print(f"[{w.name}] sources {a}..{b}: within the bar; {time.perf_counter() - t0:.0f} s",
+              flush=True)

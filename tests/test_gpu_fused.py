@@ -7,6 +7,8 @@ as for rt_columns_backward, and within the same bar of the separate
 rt_columns_backward call, whose additions run in another order.
 """
 
+import os
+
 import numpy as np
 import pytest
 import torch
@@ -214,3 +216,57 @@ def test_A_output_is_optional(rt):
     torch.cuda.synchronize()
     assert torch.equal(N.t(), N2)
     _close(g1.cpu().numpy(), g2.cpu().numpy())
+
+
+@pytest.mark.timeout(1200)
+@pytest.mark.skipif(not os.environ.get("RAYWALK_GRADIENT_512"),
+                    reason='about 25 minutes of oracle work on 16 cores, run in parts: set '
+                           'RAYWALK_GRADIENT_512="a:b" for the rays of sources a..b-1')
+def test_gradient_of_every_ray_merged_512(rt, orc):
+    """The fused pass's gradient for the rays of sources a..b-1 of the 512^3
+    cloud (RAYWALK_GRADIENT_512 = "a:b"; all: 0:134217728) against the
+    oracle's FP64 gradient of the same rays, leaf by leaf.  The loss is
+    L = sum wN N with the benchmark's seeded weights, so g = wN is known to
+    both sides without a forward pass; the A term is covered by the tests
+    above.  The oracle's gradient is summed over source blocks walked on every
+    core (its calls release the interpreter's lock) and reports as it goes."""
+    import concurrent.futures as cf
+    import time
+
+    a0, b0 = (int(x) for x in os.environ["RAYWALK_GRADIENT_512"].split(":"))
+    w = W.make_workload(4)
+    S = w.sources.shape[0]
+    assert 0 <= a0 < b0 <= S
+    dev = torch.device("cuda")
+    t = rt.Octree(w.tree.keys, w.tree.levels, w.tree.depth, dev)
+    r32 = torch.as_tensor(w.tree.rho.astype(np.float32)).to(dev)
+    dirs_h = rt.healpix_dirs(w.nside)
+    assert np.array_equal(dirs_h, orc.healpix_ring(w.nside))
+    dirs = torch.as_tensor(dirs_h).to(dev)
+    Dn = dirs.shape[0]
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(3004)
+    wN = torch.rand((Dn, S), device=dev, generator=gen).t()[a0:b0]
+    src = torch.as_tensor(w.sources[a0:b0]).to(dev)
+    _, _, grad = rt.columns_with_adjoint(t, r32, src, dirs, w.kappa, wN=wN)
+    got = grad.cpu().numpy()
+    g = wN.cpu().numpy().astype(np.float64)
+    del grad, wN, src
+    cores = max(1, min(len(os.sched_getaffinity(0)), 16))
+    bounds = np.linspace(0, b0 - a0, 8 * cores + 1).astype(np.int64)
+    want = np.zeros(w.tree.n)
+    t0 = time.perf_counter()
+
+    def block(j):
+        a, b = int(bounds[j]), int(bounds[j + 1])
+        return orc.gradient(w.tree, w.sources[a0 + a:a0 + b], dirs_h, g[a:b])
+
+    with cf.ThreadPoolExecutor(cores) as pool:
+        futures = [pool.submit(block, j) for j in range(len(bounds) - 1)]
+        for k, f in enumerate(cf.as_completed(futures)):
+            want += f.result()
+            if k % cores == cores - 1:
+                print(f"[{w.name}] oracle gradient: {k + 1} of {len(futures)} source blocks, "
+                      f"{time.perf_counter() - t0:.0f} s", flush=True)
+    _close(got, want)
+    print(f"[{w.name}] sources {a0}..{b0}: every leaf within the bar", flush=True)
